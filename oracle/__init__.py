@@ -1,0 +1,354 @@
+"""Plain FP64 CPU oracle for the H^-s distance between a triangulated surface
+and the unit sphere (or a second triangulated surface).
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+benchmark's ``cpu_baseline`` leg may import this package.  It shares no code,
+header, table or helper with the HIP library in ``paper_2304_06340_amd``; the
+only common dependency is the seeded input generator ``hsd_inputs``, which
+contains none of the method's arithmetic.
+
+Convention (reading of Section 2 used throughout): transforms are taken with
+exp(-i xi.x); the squared distance carries the Plancherel factor (2*pi)^-3 and
+the weight (1+|xi|^2)^-s with s > 0, i.e.
+
+    d^2 = (2 pi)^-3  sum_k  w_k (1+|xi_k|^2)^-s  |mu_h^(xi_k) - nu^(xi_k)|^2
+
+over the nodes xi_k and weights w_k of a quadrature on R^3 (eq. sobolev_2
+restricted to a quadrature, Section 3.2), with nu^ the sphere's transform
+4 pi sin|xi|/|xi| (eq. ft_nsphere_sinc rescaled to this convention) or the
+transform of a second mesh.
+
+Pieces, each citing what it follows:
+  * ``gauss_legendre``            -- numpy's Gauss-Legendre rule (library).
+  * ``spherical_product_rule``    -- a ball rule centred at the origin (the
+    suggestion closing Section 3.2): Gauss-Legendre panels in r, Gauss-Legendre
+    in cos(theta), trapezoid in phi.
+  * ``cube_trapezoid_rule``       -- eqs. def_trap_grid and trap_rule_R3.
+  * ``nu_hat_sphere``             -- eq. ft_nsphere_sinc in this convention.
+  * ``transform`` / ``tri_ft``    -- eq. simplex32_ft (C code, hsd_oracle.c).
+  * ``distance`` / ``gradient``   -- eq. sobolev_2 on a quadrature; gradient by
+    dual numbers (C code).
+  * ``dunavant7`` / ``gl_collapsed_rule`` / ``point_cloud`` -- eqs.
+    change_variable and change_variable_approx (Section 3.1).
+  * ``point_sum``                 -- eq. def_nufft_type1 summed directly.
+  * ``sphere_norm_paper``         -- eq. sphere_sobolev_exact (Section 4.1).
+
+Parity status: every function here is pinned by the CPU tests
+(``tests/test_oracle_*.py``) against closed forms, high-precision brute force
+or invariants; none is "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hsd_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+TAU_DEFAULT = 1e-2
+
+
+def build(force: bool = True) -> str:
+    """Compile the C part of the oracle with gcc (OpenMP, no fast-math)."""
+    if not force and os.path.exists(_LIB_PATH) and \
+            os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
+        return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+           "-std=c11", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build(force=False)
+            L = ctypes.CDLL(_LIB_PATH)
+            dp = ctypes.POINTER(ctypes.c_double)
+            ip = ctypes.POINTER(ctypes.c_int32)
+            i64 = ctypes.c_int64
+            L.oracle_tri_ft.argtypes = [dp, dp, dp, dp, ctypes.c_double, dp]
+            L.oracle_tri_ft_grad.argtypes = [dp, dp, dp, dp, ctypes.c_double, dp, dp]
+            L.oracle_transform.argtypes = [dp, i64, ip, i64, dp, dp, i64, ctypes.c_double, dp]
+            L.oracle_point_sum.argtypes = [dp, dp, i64, dp, i64, dp]
+            L.oracle_grad.argtypes = [dp, i64, ip, i64, dp, dp, dp, i64, ctypes.c_double, dp]
+            L.oracle_num_threads.restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+# --------------------------------------------------------------------------
+# frequency quadratures (Section 3.2)
+# --------------------------------------------------------------------------
+
+def gauss_legendre(n: int):
+    """n-point Gauss-Legendre nodes/weights on [-1, 1] (numpy's routine)."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    return np.asarray(x, np.float64), np.asarray(w, np.float64)
+
+
+class Rule:
+    """Flattened frequency quadrature: nodes[n,3], weights[n], radii[n]."""
+
+    def __init__(self, nodes, weights):
+        self.nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        self.weights = np.ascontiguousarray(weights, dtype=np.float64)
+        self.radii = np.linalg.norm(self.nodes, axis=1)
+
+    def __len__(self):
+        return len(self.weights)
+
+
+def spherical_product_rule(r_max: float, n_panels: int, n_per_panel: int,
+                           n_cos: int, n_phi: int) -> Rule:
+    """Product rule on the ball |xi| <= r_max (the ball-centred rule suggested
+    at the end of Section 3.2).
+
+    radial: n_panels equal panels of [0, r_max], n_per_panel Gauss-Legendre
+    nodes each; polar: Gauss-Legendre in mu = cos(theta) on [-1, 1];
+    azimuth: trapezoid phi_j = 2 pi j / n_phi.  Weight of a node:
+    w = w_r r^2 * w_mu * 2 pi / n_phi.  Node order: direction-major
+    (mu index, then phi index), radial index fastest.
+    """
+    xg, wg = gauss_legendre(n_per_panel)
+    h = r_max / n_panels
+    r, wr = [], []
+    for p in range(n_panels):
+        a = p * h
+        r.append(a + 0.5 * h * (xg + 1.0))
+        wr.append(0.5 * h * wg)
+    r = np.concatenate(r)
+    wr = np.concatenate(wr)
+    mu, wmu = gauss_legendre(n_cos)
+    phi = 2.0 * math.pi * np.arange(n_phi) / n_phi
+    st = np.sqrt(1.0 - mu * mu)
+    dirs = np.stack([
+        (st[:, None] * np.cos(phi)[None, :]).ravel(),
+        (st[:, None] * np.sin(phi)[None, :]).ravel(),
+        np.repeat(mu, n_phi),
+    ], axis=1)
+    wdir = np.repeat(wmu, n_phi) * (2.0 * math.pi / n_phi)
+    nodes = (dirs[:, None, :] * r[None, :, None]).reshape(-1, 3)
+    weights = (wdir[:, None] * (wr * r * r)[None, :]).ravel()
+    return Rule(nodes, weights)
+
+
+def cube_trapezoid_rule(xi_max: float, M: int) -> Rule:
+    """Trapezoid rule on [-xi_max, xi_max]^3 (eqs. def_trap_grid and
+    trap_rule_R3): lattice h = 2 xi_max / M, indices -M/2..M/2, weight
+    h^3 times 1, 1/2, 1/4, 1/8 on interior, faces, edges, corners."""
+    if M % 2:
+        raise ValueError("M must be even")
+    h = 2.0 * xi_max / M
+    idx = np.arange(-M // 2, M // 2 + 1)
+    w1 = np.ones(M + 1)
+    w1[0] = w1[-1] = 0.5
+    I, Jx, K = np.meshgrid(idx, idx, idx, indexing="ij")
+    nodes = np.stack([I.ravel(), Jx.ravel(), K.ravel()], axis=1) * h
+    weights = (w1[:, None, None] * w1[None, :, None] * w1[None, None, :]).ravel() * h ** 3
+    return Rule(nodes, weights)
+
+
+# --------------------------------------------------------------------------
+# sphere target (eq. ft_nsphere_sinc) and weights (eq. sobolev_2)
+# --------------------------------------------------------------------------
+
+def nu_hat_sphere(r):
+    """Transform of the unit sphere's surface measure: 4 pi sin r / r
+    (eq. ft_nsphere_sinc with xi -> xi/(2 pi)); series below r = 1e-4."""
+    r = np.asarray(r, dtype=np.float64)
+    out = np.empty_like(r)
+    small = r < 1e-4
+    rs = r[small]
+    out[small] = 4.0 * math.pi * (1.0 - rs * rs / 6.0 + rs ** 4 / 120.0)
+    rl = r[~small]
+    out[~small] = 4.0 * math.pi * np.sin(rl) / rl
+    return out
+
+
+def sobolev_weights(rule: Rule, s: float) -> np.ndarray:
+    """W_k = (2 pi)^-3 w_k (1 + |xi_k|^2)^-s."""
+    return rule.weights * (1.0 + rule.radii ** 2) ** (-s) / (2.0 * math.pi) ** 3
+
+
+# --------------------------------------------------------------------------
+# exact triangle transforms (eq. simplex32_ft)
+# --------------------------------------------------------------------------
+
+def tri_ft(v0, v1, v2, xi, tau: float = TAU_DEFAULT) -> complex:
+    out = np.zeros(2)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (v0, v1, v2, xi)]
+    lib().oracle_tri_ft(_dp(a[0]), _dp(a[1]), _dp(a[2]), _dp(a[3]), tau, _dp(out))
+    return complex(out[0], out[1])
+
+
+def tri_ft_grad(v0, v1, v2, xi, tau: float = TAU_DEFAULT):
+    """(value, d value / d(v0,v1,v2) as complex[3,3])."""
+    val = np.zeros(2)
+    out = np.zeros(18)
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (v0, v1, v2, xi)]
+    lib().oracle_tri_ft_grad(_dp(a[0]), _dp(a[1]), _dp(a[2]), _dp(a[3]), tau, _dp(val), _dp(out))
+    g = (out[0::2] + 1j * out[1::2]).reshape(3, 3)
+    return complex(val[0], val[1]), g
+
+
+def _mesh_arrays(verts, tris):
+    v = np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 3)
+    t = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+    if len(t) and (t.min() < 0 or t.max() >= len(v)):
+        raise ValueError("triangle index out of range")
+    return v, t
+
+
+def transform(verts, tris, nodes, tau: float = TAU_DEFAULT, sign=None) -> np.ndarray:
+    """mu_h^(xi_k) = sum_T mu_T^(xi_k) at nodes[n,3] -> complex[n]."""
+    v, t = _mesh_arrays(verts, tris)
+    x = np.ascontiguousarray(nodes, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(2 * len(x))
+    sg = None if sign is None else np.ascontiguousarray(sign, dtype=np.float64)
+    lib().oracle_transform(_dp(v), len(v), _ip(t), len(t),
+                           None if sg is None else _dp(sg), _dp(x), len(x), tau, _dp(out))
+    return out[0::2] + 1j * out[1::2]
+
+
+def residual(verts, tris, rule: Rule, verts2=None, tris2=None, tau: float = TAU_DEFAULT):
+    """R_k = mu_h^(xi_k) - nu^(xi_k) with nu the unit sphere (verts2 None) or
+    the second mesh."""
+    mu = transform(verts, tris, rule.nodes, tau)
+    if verts2 is None:
+        nu = nu_hat_sphere(rule.radii)
+    else:
+        nu = transform(verts2, tris2, rule.nodes, tau)
+    return mu - nu
+
+
+def distance(verts, tris, rule: Rule, s: float = 1.0, verts2=None, tris2=None,
+             tau: float = TAU_DEFAULT, return_residual: bool = False):
+    """d^2 = sum_k W_k |R_k|^2 (eq. sobolev_2 on the quadrature), summed with
+    math.fsum in node order."""
+    R = residual(verts, tris, rule, verts2, tris2, tau)
+    W = sobolev_weights(rule, s)
+    d2 = math.fsum((W * (R.real ** 2 + R.imag ** 2)).tolist())
+    return (d2, R) if return_residual else d2
+
+
+def gradient(verts, tris, rule: Rule, s: float = 1.0, verts2=None, tris2=None,
+             tau: float = TAU_DEFAULT):
+    """d(d^2)/d(verts) [nv,3] = sum_k Re(2 W_k conj(R_k) d mu_h^(xi_k)/dv),
+    with the derivative of each triangle's transform from dual numbers."""
+    v, t = _mesh_arrays(verts, tris)
+    d2, R = distance(v, t, rule, s, verts2, tris2, tau, return_residual=True)
+    W = sobolev_weights(rule, s)
+    q = 2.0 * W * np.conj(R)
+    coef = np.ascontiguousarray(np.stack([q.real, q.imag], axis=1).ravel())
+    g = np.zeros(3 * len(v))
+    x = rule.nodes
+    lib().oracle_grad(_dp(v), len(v), _ip(t), len(t), None, _dp(x), _dp(coef),
+                      len(x), tau, _dp(g))
+    return d2, g.reshape(-1, 3)
+
+
+# --------------------------------------------------------------------------
+# point-cloud model of a triangle mesh (Section 3.1) and its direct sum
+# --------------------------------------------------------------------------
+
+def dunavant7():
+    """Seven-point degree-5 symmetric rule on a triangle (Radon's rule; the
+    "more symmetric rules" Section 3.1 mentions).  Barycentric points [7,3]
+    and weights summing to 1 (multiply by the triangle area)."""
+    s15 = math.sqrt(15.0)
+    al = (6.0 - s15) / 21.0
+    be = (6.0 + s15) / 21.0
+    wa = (155.0 - s15) / 1200.0
+    wb = (155.0 + s15) / 1200.0
+    pts = [(1 / 3, 1 / 3, 1 / 3)]
+    wts = [9.0 / 40.0]
+    for x, w in ((al, wa), (be, wb)):
+        y = 1.0 - 2.0 * x
+        pts += [(x, x, y), (x, y, x), (y, x, x)]
+        wts += [w, w, w]
+    return np.array(pts), np.array(wts)
+
+
+def gl_collapsed_rule(n: int = 8):
+    """n x n Gauss-Legendre applied twice as an iterated integral on the
+    standard triangle (Section 3.1): u1 = (1+x)/2, u2 = (1-u1)(1+y)/2, weight
+    w_x w_y (1-u1)/4 * 2 (so the weights sum to 1 = area ratio 2 x 1/2).
+    Returns barycentric points [n*n,3] and weights summing to 1."""
+    x, w = gauss_legendre(n)
+    u1 = 0.5 * (x + 1.0)
+    pts, wts = [], []
+    for i in range(n):
+        for j in range(n):
+            a = u1[i]
+            b = (1.0 - a) * 0.5 * (x[j] + 1.0)
+            pts.append((1.0 - a - b, a, b))
+            wts.append(w[i] * w[j] * (1.0 - a) * 0.25 * 2.0)
+    return np.array(pts), np.array(wts)
+
+
+def point_cloud(verts, tris, rule: str = "dunavant7"):
+    """Weighted Dirac cloud {(L(u_i), q_i * area)} of every triangle
+    (eqs. change_variable, change_variable_approx).  Returns (points[np,3],
+    weights[np]) with points ordered triangle-major."""
+    v, t = _mesh_arrays(verts, tris)
+    bary, q = dunavant7() if rule == "dunavant7" else gl_collapsed_rule(8)
+    p0, p1, p2 = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+    area = 0.5 * np.linalg.norm(np.cross(p1 - p0, p2 - p0), axis=1)
+    pts = (bary[None, :, 0, None] * p0[:, None, :] + bary[None, :, 1, None] * p1[:, None, :]
+           + bary[None, :, 2, None] * p2[:, None, :])
+    c = area[:, None] * q[None, :]
+    return pts.reshape(-1, 3), c.ravel()
+
+
+def point_sum(points, c, nodes) -> np.ndarray:
+    """sum_j c_j exp(-i xi_k . x_j) evaluated directly (complex[n])."""
+    p = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 3)
+    cc = np.ascontiguousarray(c, dtype=np.float64)
+    x = np.ascontiguousarray(nodes, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros(2 * len(x))
+    lib().oracle_point_sum(_dp(p), _dp(cc), len(p), _dp(x), len(x), _dp(out))
+    return out[0::2] + 1j * out[1::2]
+
+
+# --------------------------------------------------------------------------
+# closed forms
+# --------------------------------------------------------------------------
+
+def sphere_norm_paper(s: float) -> float:
+    """||sigma||^2_{H_s} in the paper's exp(-2 pi i xi.x) convention,
+    eq. sphere_sobolev_exact (s < -1/2)."""
+    from scipy.special import gamma, kv
+    nu = -s - 0.5
+    return 4.0 * math.pi ** 1.5 / gamma(-s) * (gamma(nu) - 2.0 * (2.0 * math.pi) ** nu * kv(nu, 4.0 * math.pi))
+
+
+def empty_mesh_distance_radial(rule_r, rule_wr, s: float = 1.0) -> float:
+    """d^2 between the empty surface and S^2 for a product rule whose angular
+    part integrates constants exactly: 8 sum_r w_r sin^2 r (1+r^2)^-s
+    (the angular integral of |nu^|^2 is 4 pi * 16 pi^2 sin^2 r / r^2)."""
+    r = np.asarray(rule_r)
+    return 8.0 * math.fsum((np.asarray(rule_wr) * np.sin(r) ** 2 * (1.0 + r * r) ** (-s)).tolist())
