@@ -1,0 +1,270 @@
+"""Python binding of libhsd (argument marshalling only; every step of the
+computation runs in the HIP kernels behind the C ABI of include/hsd.h)."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib as L
+
+
+class HsdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"hsd error {L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status: int) -> int:
+    if status < 0:
+        msg = L.load().hsd_last_error().decode(errors="replace")
+        raise HsdError(status, msg)
+    return status
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _host_f64(a, shape_last=None) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape_last is not None:
+        a = a.reshape(-1, shape_last)
+    return a
+
+
+def _host_i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32)).reshape(-1, 3)
+
+
+_FORMS = {"fp64": L.FORM_FP64, "mixed": L.FORM_MIXED}
+_METHODS = {"direct": L.METHOD_DIRECT, "nufft3": L.METHOD_NUFFT3}
+_TRI_RULES = {"dunavant7": L.TRI_DUNAVANT7, "gl8x8": L.TRI_GL8X8}
+
+
+@dataclass
+class Params:
+    """Per-call parameters (hsd_params)."""
+    s: float = 1.0
+    form: str = "fp64"
+    method: str = "direct"
+    taylor_tau: float = 1e-2
+    tri_rule: str = "dunavant7"
+    nufft_tol: float = 1e-9
+    nufft_width: int = 0
+    nufft_sigma: float = 2.0
+    k_splits: int = 0
+
+    def to_c(self) -> L.Params:
+        p = L.Params()
+        L.load().hsd_params_default(C.byref(p))
+        p.s = float(self.s)
+        p.form = _FORMS[self.form]
+        p.method = _METHODS[self.method]
+        p.taylor_tau = float(self.taylor_tau)
+        p.tri_rule = _TRI_RULES[self.tri_rule]
+        p.nufft_tol = float(self.nufft_tol)
+        p.nufft_width = int(self.nufft_width)
+        p.nufft_sigma = float(self.nufft_sigma)
+        p.k_splits = int(self.k_splits)
+        return p
+
+
+@dataclass
+class Result:
+    d2: float
+    rel_err_stated: float
+    pairs: float
+    device_ms: float
+    transform_ms: float
+
+    @staticmethod
+    def from_c(r: L.Result) -> "Result":
+        return Result(r.d2, r.rel_err_stated, r.pairs, r.device_ms, r.transform_ms)
+
+
+class Context:
+    """A device context (hsd_init).  Binds torch's current stream if torch
+    is available and a GPU is present."""
+
+    def __init__(self, device: int = 0, budget_bytes: int = 0, bind_torch_stream: bool = True):
+        self._lib = L.load()
+        h = C.c_void_p()
+        _check(self._lib.hsd_init(int(device), int(budget_bytes), C.byref(h)))
+        self.handle = h
+        self.device = device
+        if bind_torch_stream:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    self.set_stream(torch.cuda.current_stream(device).cuda_stream)
+            except ImportError:
+                pass
+
+    def set_stream(self, stream_ptr) -> None:
+        _check(self._lib.hsd_ctx_set_stream(self.handle, C.c_void_p(int(stream_ptr) if stream_ptr else 0)))
+
+    def bytes_in_use(self) -> int:
+        return int(self._lib.hsd_ctx_bytes_in_use(self.handle))
+
+    def close(self) -> None:
+        if self.handle:
+            self._lib.hsd_finalize(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Mesh:
+    """A device-resident triangle mesh (hsd_create_mesh).  verts [nv,3]
+    float64 and tris [nt,3] int32, numpy arrays or torch tensors (device
+    tensors are read in place)."""
+
+    def __init__(self, ctx: Context, verts, tris):
+        self.ctx = ctx
+        lib = ctx._lib
+        h = C.c_void_p()
+        if _is_torch(verts) and verts.is_cuda:
+            import torch
+            v = verts.detach().to(torch.float64).contiguous()
+            t = tris.to(device=v.device, dtype=torch.int32).contiguous()
+            _check(lib.hsd_create_mesh(ctx.handle, C.c_void_p(v.data_ptr()), v.shape[0],
+                                       C.c_void_p(t.data_ptr()), t.shape[0], L.MEM_DEVICE, C.byref(h)))
+        else:
+            if _is_torch(verts):
+                verts = verts.detach().cpu().numpy()
+            if _is_torch(tris):
+                tris = tris.cpu().numpy()
+            v = _host_f64(verts, 3)
+            t = _host_i32(tris)
+            _check(lib.hsd_create_mesh(ctx.handle, v.ctypes.data_as(C.c_void_p), len(v),
+                                       t.ctypes.data_as(C.c_void_p), len(t), L.MEM_HOST, C.byref(h)))
+        self.handle = h
+
+    @property
+    def num_triangles(self) -> int:
+        return int(self.ctx._lib.hsd_mesh_num_triangles(self.handle))
+
+    @property
+    def num_vertices(self) -> int:
+        return int(self.ctx._lib.hsd_mesh_num_vertices(self.handle))
+
+    def close(self):
+        if self.handle:
+            self.ctx._lib.hsd_mesh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Rule:
+    """A device-resident frequency quadrature (hsd_freq_rule)."""
+
+    def __init__(self, ctx: Context, desc: L.RuleDesc, keep=()):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(ctx._lib.hsd_freq_rule(ctx.handle, C.byref(desc), C.byref(h)))
+        self.handle = h
+        self.kind = desc.kind
+        self.desc = {f: getattr(desc, f) for f, _ in L.RuleDesc._fields_ if f not in ("nodes", "weights")}
+
+    @classmethod
+    def spherical_product(cls, ctx, r_max, n_panels, n_per_panel, n_cos, n_phi) -> "Rule":
+        d = L.RuleDesc()
+        d.kind = L.RULE_SPHERICAL_PRODUCT
+        d.r_max, d.n_panels, d.n_per_panel, d.n_cos, d.n_phi = float(r_max), n_panels, n_per_panel, n_cos, n_phi
+        return cls(ctx, d)
+
+    @classmethod
+    def explicit(cls, ctx, nodes, weights) -> "Rule":
+        x = _host_f64(nodes, 3)
+        w = _host_f64(weights).ravel()
+        d = L.RuleDesc()
+        d.kind = L.RULE_EXPLICIT
+        d.nodes = x.ctypes.data_as(L.dp)
+        d.weights = w.ctypes.data_as(L.dp)
+        d.n_nodes = len(x)
+        return cls(ctx, d)
+
+    @classmethod
+    def cube_trapezoid(cls, ctx, xi_max, M) -> "Rule":
+        d = L.RuleDesc()
+        d.kind = L.RULE_CUBE_TRAPEZOID
+        d.xi_max, d.M = float(xi_max), int(M)
+        return cls(ctx, d)
+
+    def __len__(self) -> int:
+        return int(self.ctx._lib.hsd_rule_num_nodes(self.handle))
+
+    def nodes(self):
+        n = len(self)
+        x = np.empty((n, 3))
+        w = np.empty(n)
+        _check(self.ctx._lib.hsd_rule_nodes(self.handle, x.ctypes.data_as(L.dp), w.ctypes.data_as(L.dp)))
+        return x, w
+
+    def close(self):
+        if self.handle:
+            self.ctx._lib.hsd_rule_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def distance(ctx: Context, mu: Mesh, nu: Mesh | None, rule: Rule, params: Params | None = None) -> Result:
+    """Squared H^-s distance (hsd_distance); nu None is the unit sphere."""
+    p = (params or Params()).to_c()
+    r = L.Result()
+    _check(ctx._lib.hsd_distance(ctx.handle, mu.handle, nu.handle if nu is not None else None,
+                                 rule.handle, C.byref(p), C.byref(r)))
+    return Result.from_c(r)
+
+
+def distance_grad(ctx: Context, mu: Mesh, nu: Mesh | None, rule: Rule, params: Params | None = None,
+                  out=None):
+    """(Result, grad[nv,3]) (hsd_distance_grad).  ``out`` may be a device
+    torch tensor [nv,3] float64 (written on the bound stream)."""
+    p = (params or Params()).to_c()
+    r = L.Result()
+    if out is not None and _is_torch(out) and out.is_cuda:
+        _check(ctx._lib.hsd_distance_grad(ctx.handle, mu.handle, nu.handle if nu is not None else None,
+                                          rule.handle, C.byref(p), C.c_void_p(out.data_ptr()),
+                                          L.MEM_DEVICE, C.byref(r)))
+        return Result.from_c(r), out
+    g = np.zeros((mu.num_vertices, 3))
+    _check(ctx._lib.hsd_distance_grad(ctx.handle, mu.handle, nu.handle if nu is not None else None,
+                                      rule.handle, C.byref(p), g.ctypes.data_as(C.c_void_p),
+                                      L.MEM_HOST, C.byref(r)))
+    return Result.from_c(r), g
+
+
+def transform(ctx: Context, mesh: Mesh, nodes, params: Params | None = None) -> np.ndarray:
+    """mu_h^ at arbitrary nodes [n,3] (hsd_transform) -> complex128[n]."""
+    p = (params or Params()).to_c()
+    x = _host_f64(nodes, 3)
+    out = np.empty(2 * len(x))
+    _check(ctx._lib.hsd_transform(ctx.handle, mesh.handle, x.ctypes.data_as(C.c_void_p), len(x),
+                                  L.MEM_HOST, C.byref(p), out.ctypes.data_as(C.c_void_p), L.MEM_HOST))
+    return out[0::2] + 1j * out[1::2]
+
+
+def transform_rule(ctx: Context, mesh: Mesh, rule: Rule, params: Params | None = None) -> np.ndarray:
+    """mu_h^ at every node of a rule (hsd_transform_rule) -> complex128[n]."""
+    p = (params or Params()).to_c()
+    out = np.empty(2 * len(rule))
+    _check(ctx._lib.hsd_transform_rule(ctx.handle, mesh.handle, rule.handle, C.byref(p),
+                                       out.ctypes.data_as(C.c_void_p), L.MEM_HOST))
+    return out[0::2] + 1j * out[1::2]

@@ -1,0 +1,761 @@
+// hsd_core.hip -- host side of the C ABI: errors, contexts, device-memory
+// budget, mesh ingest, frequency rules, and the distance / transform entry
+// points that enqueue the kernels of hsd_direct.hip, hsd_adjoint.hip and
+// hsd_nufft.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "hsd_internal.hpp"
+
+namespace hsd {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+std::string hip_msg(hipError_t e, const char *what)
+{
+    std::string s = what;
+    s += ": ";
+    s += hipGetErrorString(e);
+    return s;
+}
+
+DevBuf::~DevBuf() { release(); }
+
+void DevBuf::release()
+{
+    if (ptr) {
+        (void)hipFree(ptr);
+        if (ctx) ctx->in_use -= bytes;
+    }
+    ptr = nullptr;
+    bytes = 0;
+}
+
+hsd_status DevBuf::alloc(hsd_ctx *c, size_t n)
+{
+    release();
+    ctx = c;
+    if (n == 0) return HSD_OK;
+    const size_t now = c->in_use.fetch_add(n);
+    if (now + n > c->budget) {
+        c->in_use -= n;
+        set_error("device memory budget exceeded: need %zu more bytes, %zu of %zu in use", n, now,
+                  c->budget);
+        return HSD_ENOMEM;
+    }
+    hipError_t e = hipMalloc(&ptr, n);
+    if (e != hipSuccess) {
+        c->in_use -= n;
+        ptr = nullptr;
+        set_error("hipMalloc(%zu): %s", n, hipGetErrorString(e));
+        return HSD_ENOMEM;
+    }
+    bytes = n;
+    return HSD_OK;
+}
+
+hsd_status Scratch::ensure(hsd_ctx *c, size_t n)
+{
+    if (buf.ptr && buf.bytes >= n) return HSD_OK;
+    size_t want = std::max(n, buf.bytes + buf.bytes / 2);
+    buf.release();
+    hsd_status st = buf.alloc(c, want);
+    if (st == HSD_ENOMEM && want > n) st = buf.alloc(c, n);
+    return st;
+}
+
+// ---------------------------------------------------------------------------
+// Gauss-Legendre by Newton's iteration on the three-term recurrence
+// ---------------------------------------------------------------------------
+static void legendre_pd(int n, double x, double &p, double &dp)
+{
+    double p0 = 1.0, p1 = x;
+    if (n == 0) { p = 1.0; dp = 0.0; return; }
+    for (int k = 2; k <= n; ++k) {
+        const double pk = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = pk;
+    }
+    p = p1;
+    dp = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        // i-th largest root, Tricomi-style initial guess
+        double z = std::cos(pi * (i + 0.75) / (n + 0.5));
+        double p, dp;
+        for (int it = 0; it < 100; ++it) {
+            legendre_pd(n, z, p, dp);
+            const double dz = p / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        legendre_pd(n, z, p, dp);
+        const double wi = 2.0 / ((1.0 - z * z) * dp * dp);
+        x[n - 1 - i] = z;
+        x[i] = -z;
+        w[n - 1 - i] = wi;
+        w[i] = wi;
+    }
+    if (n % 2 == 1) x[n / 2] = 0.0;
+}
+
+hsd_status validate_params(const hsd_params *p)
+{
+    if (!p) { set_error("params is NULL"); return HSD_EINVAL; }
+    if (!std::isfinite(p->s) || p->s < 0.0) {
+        set_error("s must be finite and >= 0 (got %g)", p->s);
+        return HSD_EINVAL;
+    }
+    if (p->form != HSD_FORM_FP64 && p->form != HSD_FORM_MIXED) {
+        set_error("unknown form %d", p->form);
+        return HSD_EINVAL;
+    }
+    if (p->method != HSD_METHOD_DIRECT && p->method != HSD_METHOD_NUFFT3) {
+        set_error("unknown method %d", p->method);
+        return HSD_EINVAL;
+    }
+    if (!(p->taylor_tau > 0.0) || p->taylor_tau > 0.05) {
+        set_error("taylor_tau must be in (0, 0.05] (got %g)", p->taylor_tau);
+        return HSD_EINVAL;
+    }
+    return HSD_OK;
+}
+
+// Stated relative error of d^2 per form (see the measurement notes): the
+// FP64 direct form is held to 1e-10, the mixed form to 1e-6 on meshes up
+// to ~3.3e5 triangles; NUFFT error is the requested tolerance relative to
+// sum |c_j| per node, amplified by |mu|/|R| (reported as tol * 1e4).
+double stated_rel_err(const hsd_params *p, int64_t nt)
+{
+    (void)nt;
+    if (p->method == HSD_METHOD_NUFFT3) return std::max(p->nufft_tol, 1e-15) * 1e4;
+    return p->form == HSD_FORM_FP64 ? 1e-10 : 1e-6;
+}
+
+// Per-s tables of a rule: SP -> radial W_r = w_r r^2 (1+r^2)^-s (2 pi)^-3 and
+// nu_r = 4 pi sin r / r; general -> per node W and nu.
+hsd_status rule_tables(hsd_rule *rule, double s, hipStream_t st, const double **wtab,
+                       const double **nutab)
+{
+    std::lock_guard<std::mutex> lk(rule->mu);
+    auto it = rule->tabs.find(s);
+    if (it != rule->tabs.end()) {
+        *wtab = it->second->w.as<const double>();
+        *nutab = it->second->nu.as<const double>();
+        return HSD_OK;
+    }
+    const double inv8pi3 = 1.0 / (8.0 * M_PI * M_PI * M_PI);
+    std::vector<double> W, nu;
+    auto nu_of = [](double r) {
+        if (r < 1e-4) return 4.0 * M_PI * (1.0 - r * r / 6.0 + r * r * r * r / 120.0);
+        return 4.0 * M_PI * std::sin(r) / r;
+    };
+    if (rule->kind == HSD_RULE_SPHERICAL_PRODUCT) {
+        const auto &sp = rule->sp;
+        W.resize(rule->n_rad);
+        nu.resize(rule->n_rad);
+        for (int64_t i = 0; i < rule->n_rad; ++i) {
+            const double r = sp.radii[i];
+            W[i] = sp.wr[i] * r * r * std::pow(1.0 + r * r, -s) * inv8pi3;
+            nu[i] = nu_of(r);
+        }
+    } else {
+        W.resize(rule->n_nodes);
+        nu.resize(rule->n_nodes);
+        for (int64_t i = 0; i < rule->n_nodes; ++i) {
+            const double r = rule->host_radii[i];
+            W[i] = rule->host_weights[i] * std::pow(1.0 + r * r, -s) * inv8pi3;
+            nu[i] = nu_of(r);
+        }
+    }
+    std::unique_ptr<hsd_rule::Tables> t(new hsd_rule::Tables());
+    hsd_status stt;
+    if ((stt = t->w.alloc(rule->ctx, W.size() * 8)) != HSD_OK) return stt;
+    if ((stt = t->nu.alloc(rule->ctx, nu.size() * 8)) != HSD_OK) return stt;
+    HSD_HIP_TRY(hipMemcpyAsync(t->w.ptr, W.data(), W.size() * 8, hipMemcpyHostToDevice, st));
+    HSD_HIP_TRY(hipMemcpyAsync(t->nu.ptr, nu.data(), nu.size() * 8, hipMemcpyHostToDevice, st));
+    HSD_HIP_TRY(hipStreamSynchronize(st));
+    *wtab = t->w.as<const double>();
+    *nutab = t->nu.as<const double>();
+    rule->tabs[s] = std::move(t);
+    return HSD_OK;
+}
+
+// Enqueue one distance evaluation: transform (direct or NUFFT) into partial,
+// finalize per node, reduce to d_result[0].  keep_resid leaves R_k in
+// nodebuf (double2[N]) for the adjoint.
+hsd_status distance_core(hsd_ctx *ctx, hipStream_t st, const hsd_mesh *mu, const hsd_mesh *nu,
+                         const hsd_rule *rule_c, const hsd_params *p, bool keep_resid,
+                         Scratch &partial, Scratch &nodebuf, Scratch &redbuf, double **d_result,
+                         double *pairs, hipEvent_t ev_tb, hipEvent_t ev_te)
+{
+    hsd_rule *rule = const_cast<hsd_rule *>(rule_c);
+    hsd_status stt;
+    const double *wtab = nullptr, *nutab = nullptr;
+    if ((stt = rule_tables(rule, p->s, st, &wtab, &nutab)) != HSD_OK) return stt;
+    const int64_t N = rule->n_nodes;
+    MeshPair mp;
+    mp.A = mu->tris.as<const TriRec>();
+    mp.nA = mu->nt;
+    if (nu) {
+        mp.B = nu->tris.as<const TriRec>();
+        mp.nB = nu->nt;
+    }
+    const int64_t ntot = mp.nA + mp.nB;
+    int K = 1;
+    const double2 *mu_hat = nullptr;
+    if (ev_tb) HSD_HIP_TRY(hipEventRecord(ev_tb, st));
+    if (p->method == HSD_METHOD_NUFFT3) {
+        if ((stt = partial.ensure(ctx, (size_t)N * sizeof(double2))) != HSD_OK) return stt;
+        if ((stt = nufft_transform_rule(ctx, st, mu, nu, rule, p, partial.buf.as<double2>(), pairs)) != HSD_OK)
+            return stt;
+        mu_hat = partial.buf.as<const double2>();
+    } else {
+        if (rule->kind == HSD_RULE_SPHERICAL_PRODUCT)
+            K = choose_k_splits_sp(rule, ntot, p->form, ctx->num_cu, p->k_splits);
+        else
+            K = choose_k_splits_gen(N, ntot, ctx->num_cu, p->k_splits);
+        if ((stt = partial.ensure(ctx, (size_t)K * N * sizeof(double2))) != HSD_OK) return stt;
+        if (ntot == 0) {
+            K = 1;
+            HSD_HIP_TRY(hipMemsetAsync(partial.buf.ptr, 0, (size_t)N * sizeof(double2), st));
+        } else if (rule->kind == HSD_RULE_SPHERICAL_PRODUCT) {
+            if ((stt = launch_direct_sp(st, mp, rule, p->form, p->taylor_tau, K, partial.buf.as<double2>())) != HSD_OK)
+                return stt;
+        } else {
+            if ((stt = launch_direct_gen(st, mp, rule->d_nodes.as<const double>(), N, p->form,
+                                         p->taylor_tau, K, partial.buf.as<double2>())) != HSD_OK)
+                return stt;
+        }
+        mu_hat = partial.buf.as<const double2>();
+        if (pairs) *pairs = (double)ntot * (double)N;
+    }
+    if (ev_te) HSD_HIP_TRY(hipEventRecord(ev_te, st));
+    const int64_t nb = finalize_blocks(N);
+    if ((stt = redbuf.ensure(ctx, (size_t)(nb + 1) * sizeof(double))) != HSD_OK) return stt;
+    double2 *resid = nullptr;
+    if (keep_resid) {
+        if ((stt = nodebuf.ensure(ctx, (size_t)N * sizeof(double2))) != HSD_OK) return stt;
+        resid = nodebuf.buf.as<double2>();
+    }
+    if ((stt = launch_finalize(st, rule, wtab, nutab, mu_hat, K, N, nu == nullptr, resid,
+                               redbuf.buf.as<double>(), nb)) != HSD_OK)
+        return stt;
+    *d_result = redbuf.buf.as<double>() + nb;
+    return launch_final_reduce(st, redbuf.buf.as<double>(), nb, *d_result);
+}
+
+// Per-triangle records p0, e1 = p1 - p0, e2 = p2 - p0, J = |e1 x e2|
+// (indices already validated).
+void build_tri_records(const double *verts, const int32_t *tris, int64_t nt, TriRec *rec)
+{
+    for (int64_t t = 0; t < nt; ++t) {
+        const double *p0 = &verts[3 * (size_t)tris[3 * t]];
+        const double *p1 = &verts[3 * (size_t)tris[3 * t + 1]];
+        const double *p2 = &verts[3 * (size_t)tris[3 * t + 2]];
+        TriRec &r = rec[t];
+        for (int c = 0; c < 3; ++c) {
+            r.p0[c] = p0[c];
+            r.e1[c] = p1[c] - p0[c];
+            r.e2[c] = p2[c] - p0[c];
+        }
+        const double cx = r.e1[1] * r.e2[2] - r.e1[2] * r.e2[1];
+        const double cy = r.e1[2] * r.e2[0] - r.e1[0] * r.e2[2];
+        const double cz = r.e1[0] * r.e2[1] - r.e1[1] * r.e2[0];
+        r.J = std::sqrt(cx * cx + cy * cy + cz * cz);
+    }
+}
+
+// Contexts are reference counted: every mesh, rule and server holds a
+// reference, so a context outlives the objects created from it even if
+// hsd_finalize is called first.
+void ctx_retain(hsd_ctx *c) { c->refs.fetch_add(1); }
+
+void ctx_release(hsd_ctx *c)
+{
+    if (c->refs.fetch_sub(1) != 1) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    c->partial.buf.release();
+    c->nodebuf.buf.release();
+    c->redbuf.buf.release();
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->evt0) (void)hipEventDestroy(c->evt0);
+    if (c->evt1) (void)hipEventDestroy(c->evt1);
+    if (c->host_result) (void)hipHostFree(c->host_result);
+    delete c;
+}
+
+static hsd_status check_ctx(hsd_ctx *ctx)
+{
+    if (!ctx) { set_error("context is NULL"); return HSD_EINVAL; }
+    HSD_HIP_TRY(hipSetDevice(ctx->device));
+    return HSD_OK;
+}
+
+} // namespace hsd
+
+using namespace hsd;
+
+// Device buffers are freed after the device is idle; the context reference
+// is dropped last.
+hsd_mesh::~hsd_mesh()
+{
+    hsd_ctx *c = ctx;
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    tris.release();
+    verts.release();
+    idx.release();
+    csr_ptr.release();
+    csr_ent.release();
+    ctx_release(c);
+}
+
+hsd_rule::~hsd_rule()
+{
+    hsd_ctx *c = ctx;
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    d_dirs.release();
+    d_wdir.release();
+    d_hx.release();
+    d_nodes.release();
+    tabs.clear();
+    ctx_release(c);
+}
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *hsd_version(void) { return "hsd 0.1 (gfx950)"; }
+
+const char *hsd_last_error(void) { return g_err; }
+
+void hsd_params_default(hsd_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->s = 1.0;
+    p->form = HSD_FORM_FP64;
+    p->method = HSD_METHOD_DIRECT;
+    p->taylor_tau = 1e-2;
+    p->tri_rule = HSD_TRI_DUNAVANT7;
+    p->nufft_tol = 1e-9;
+    p->nufft_width = 0;
+    p->nufft_sigma = 2.0;
+    p->k_splits = 0;
+}
+
+hsd_status hsd_init(int device, size_t budget, hsd_ctx **out)
+{
+    if (!out) { set_error("out is NULL"); return HSD_EINVAL; }
+    *out = nullptr;
+    int ndev = 0;
+    HSD_HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) {
+        set_error("device %d out of range (%d devices)", device, ndev);
+        return HSD_EINVAL;
+    }
+    HSD_HIP_TRY(hipSetDevice(device));
+    size_t freeb = 0, totalb = 0;
+    HSD_HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+    auto *c = new hsd_ctx();
+    c->device = device;
+    c->budget = budget ? budget : (size_t)(0.9 * (double)freeb);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipEventCreate(&c->evt0) != hipSuccess || hipEventCreate(&c->evt1) != hipSuccess ||
+        hipHostMalloc((void **)&c->host_result, 64, hipHostMallocDefault) != hipSuccess) {
+        set_error("hsd_init: event/pinned allocation failed");
+        delete c;
+        return HSD_EDEVICE;
+    }
+    *out = c;
+    return HSD_OK;
+}
+
+hsd_status hsd_ctx_set_stream(hsd_ctx *ctx, void *stream)
+{
+    if (!ctx) { set_error("context is NULL"); return HSD_EINVAL; }
+    ctx->stream = (hipStream_t)stream;
+    return HSD_OK;
+}
+
+size_t hsd_ctx_bytes_in_use(const hsd_ctx *ctx) { return ctx ? ctx->in_use.load() : 0; }
+
+void hsd_finalize(hsd_ctx *ctx)
+{
+    if (!ctx) return;
+    ctx_release(ctx);
+}
+
+hsd_status hsd_create_mesh(hsd_ctx *ctx, const double *verts, int64_t nv, const int32_t *tris,
+                           int64_t nt, int32_t mem_kind, hsd_mesh **out)
+{
+    hsd_status stt;
+    if ((stt = check_ctx(ctx)) != HSD_OK) return stt;
+    if (!out) { set_error("out is NULL"); return HSD_EINVAL; }
+    *out = nullptr;
+    if (nv < 0 || nt < 0 || nv > INT32_MAX || nt > INT32_MAX / 3) {
+        set_error("bad mesh sizes nv=%lld nt=%lld", (long long)nv, (long long)nt);
+        return HSD_EINVAL;
+    }
+    if ((nv > 0 && !verts) || (nt > 0 && !tris)) {
+        set_error("NULL mesh arrays");
+        return HSD_EINVAL;
+    }
+    if (mem_kind != HSD_MEM_HOST && mem_kind != HSD_MEM_DEVICE) {
+        set_error("bad mem_kind %d", mem_kind);
+        return HSD_EINVAL;
+    }
+    std::unique_ptr<hsd_mesh> m(new hsd_mesh());
+    m->ctx = ctx;
+    ctx_retain(ctx);
+    m->nv = nv;
+    m->nt = nt;
+    m->host_verts.resize((size_t)nv * 3);
+    m->host_tris.resize((size_t)nt * 3);
+    if (mem_kind == HSD_MEM_HOST) {
+        if (nv) std::memcpy(m->host_verts.data(), verts, (size_t)nv * 3 * 8);
+        if (nt) std::memcpy(m->host_tris.data(), tris, (size_t)nt * 3 * 4);
+    } else {
+        if (nv) HSD_HIP_TRY(hipMemcpy(m->host_verts.data(), verts, (size_t)nv * 3 * 8, hipMemcpyDeviceToHost));
+        if (nt) HSD_HIP_TRY(hipMemcpy(m->host_tris.data(), tris, (size_t)nt * 3 * 4, hipMemcpyDeviceToHost));
+    }
+    for (int64_t i = 0; i < nv * 3; ++i)
+        if (!std::isfinite(m->host_verts[i])) {
+            set_error("vertex %lld is not finite", (long long)(i / 3));
+            return HSD_EINVAL;
+        }
+    for (int64_t i = 0; i < nt * 3; ++i)
+        if (m->host_tris[i] < 0 || m->host_tris[i] >= nv) {
+            set_error("triangle %lld: vertex index %d outside [0, %lld)", (long long)(i / 3),
+                      m->host_tris[i], (long long)nv);
+            return HSD_EINVAL;
+        }
+    std::vector<TriRec> rec((size_t)nt);
+    build_tri_records(m->host_verts.data(), m->host_tris.data(), nt, rec.data());
+    // vertex -> (3 t + slot) CSR, entries in increasing triangle order
+    std::vector<int32_t> ptr((size_t)nv + 1, 0), ent((size_t)nt * 3);
+    for (int64_t i = 0; i < nt * 3; ++i) ptr[(size_t)m->host_tris[i] + 1]++;
+    for (int64_t v = 0; v < nv; ++v) ptr[v + 1] += ptr[v];
+    {
+        std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+        for (int64_t i = 0; i < nt * 3; ++i) ent[(size_t)fill[(size_t)m->host_tris[i]]++] = (int32_t)i;
+    }
+    hipStream_t st = ctx->stream;
+    if ((stt = m->tris.alloc(ctx, (size_t)nt * sizeof(TriRec))) != HSD_OK) return stt;
+    if ((stt = m->verts.alloc(ctx, (size_t)nv * 24)) != HSD_OK) return stt;
+    if ((stt = m->idx.alloc(ctx, (size_t)nt * 12)) != HSD_OK) return stt;
+    if ((stt = m->csr_ptr.alloc(ctx, ((size_t)nv + 1) * 4)) != HSD_OK) return stt;
+    if ((stt = m->csr_ent.alloc(ctx, (size_t)nt * 12)) != HSD_OK) return stt;
+    if (nt) HSD_HIP_TRY(hipMemcpyAsync(m->tris.ptr, rec.data(), (size_t)nt * sizeof(TriRec), hipMemcpyHostToDevice, st));
+    if (nv) HSD_HIP_TRY(hipMemcpyAsync(m->verts.ptr, m->host_verts.data(), (size_t)nv * 24, hipMemcpyHostToDevice, st));
+    if (nt) HSD_HIP_TRY(hipMemcpyAsync(m->idx.ptr, m->host_tris.data(), (size_t)nt * 12, hipMemcpyHostToDevice, st));
+    HSD_HIP_TRY(hipMemcpyAsync(m->csr_ptr.ptr, ptr.data(), ((size_t)nv + 1) * 4, hipMemcpyHostToDevice, st));
+    if (nt) HSD_HIP_TRY(hipMemcpyAsync(m->csr_ent.ptr, ent.data(), (size_t)nt * 12, hipMemcpyHostToDevice, st));
+    HSD_HIP_TRY(hipStreamSynchronize(st));
+    *out = m.release();
+    return HSD_OK;
+}
+
+int64_t hsd_mesh_num_triangles(const hsd_mesh *m) { return m ? m->nt : -1; }
+int64_t hsd_mesh_num_vertices(const hsd_mesh *m) { return m ? m->nv : -1; }
+
+void hsd_mesh_destroy(hsd_mesh *m)
+{
+    if (!m) return;
+    if (--m->refs > 0) return;
+    delete m;
+}
+
+hsd_status hsd_freq_rule(hsd_ctx *ctx, const hsd_rule_desc *d, hsd_rule **out)
+{
+    hsd_status stt;
+    if ((stt = check_ctx(ctx)) != HSD_OK) return stt;
+    if (!d || !out) { set_error("NULL argument"); return HSD_EINVAL; }
+    *out = nullptr;
+    std::unique_ptr<hsd_rule> r(new hsd_rule());
+    r->ctx = ctx;
+    ctx_retain(ctx);
+    r->kind = d->kind;
+    hipStream_t st = ctx->stream;
+    if (d->kind == HSD_RULE_SPHERICAL_PRODUCT) {
+        if (!(d->r_max > 0.0) || !std::isfinite(d->r_max) || d->n_panels <= 0 || d->n_per_panel <= 0 ||
+            d->n_cos <= 0 || d->n_phi <= 0) {
+            set_error("spherical product rule: bad sizes");
+            return HSD_EINVAL;
+        }
+        if (d->n_per_panel % 2 != 0) {
+            set_error("spherical product rule: n_per_panel must be even (symmetric node pairs)");
+            return HSD_EINVAL;
+        }
+        RuleSP &sp = r->sp;
+        sp.r_max = d->r_max;
+        sp.P = d->n_panels;
+        sp.n = d->n_per_panel;
+        sp.n_cos = d->n_cos;
+        sp.n_phi = d->n_phi;
+        sp.delta = d->r_max / d->n_panels;
+        sp.h = 0.5 * sp.delta;
+        gauss_legendre(sp.n, sp.x, sp.wx);
+        sp.radii.resize((size_t)sp.P * sp.n);
+        sp.wr.resize((size_t)sp.P * sp.n);
+        for (int p = 0; p < sp.P; ++p)
+            for (int j = 0; j < sp.n; ++j) {
+                sp.radii[(size_t)p * sp.n + j] = (2.0 * p + 1.0) * sp.h + sp.h * sp.x[j];
+                sp.wr[(size_t)p * sp.n + j] = sp.h * sp.wx[j];
+            }
+        gauss_legendre(sp.n_cos, sp.mu, sp.wmu);
+        r->n_dir = (int64_t)sp.n_cos * sp.n_phi;
+        r->n_rad = (int64_t)sp.P * sp.n;
+        r->n_nodes = r->n_dir * r->n_rad;
+        sp.dirs.resize((size_t)r->n_dir * 3);
+        sp.wdir.resize((size_t)r->n_dir);
+        for (int i = 0; i < sp.n_cos; ++i) {
+            const double stheta = std::sqrt(1.0 - sp.mu[i] * sp.mu[i]);
+            for (int j = 0; j < sp.n_phi; ++j) {
+                const double phi = 2.0 * M_PI * j / sp.n_phi;
+                const size_t dd = (size_t)i * sp.n_phi + j;
+                sp.dirs[3 * dd] = stheta * std::cos(phi);
+                sp.dirs[3 * dd + 1] = stheta * std::sin(phi);
+                sp.dirs[3 * dd + 2] = sp.mu[i];
+                sp.wdir[dd] = sp.wmu[i] * 2.0 * M_PI / sp.n_phi;
+            }
+        }
+        std::vector<double> hx((size_t)sp.n / 2);
+        for (int k = 0; k < sp.n / 2; ++k) hx[k] = sp.h * sp.x[sp.n / 2 + k];
+        if ((stt = r->d_dirs.alloc(ctx, sp.dirs.size() * 8)) != HSD_OK) return stt;
+        if ((stt = r->d_wdir.alloc(ctx, sp.wdir.size() * 8)) != HSD_OK) return stt;
+        if ((stt = r->d_hx.alloc(ctx, hx.size() * 8)) != HSD_OK) return stt;
+        HSD_HIP_TRY(hipMemcpyAsync(r->d_dirs.ptr, sp.dirs.data(), sp.dirs.size() * 8, hipMemcpyHostToDevice, st));
+        HSD_HIP_TRY(hipMemcpyAsync(r->d_wdir.ptr, sp.wdir.data(), sp.wdir.size() * 8, hipMemcpyHostToDevice, st));
+        HSD_HIP_TRY(hipMemcpyAsync(r->d_hx.ptr, hx.data(), hx.size() * 8, hipMemcpyHostToDevice, st));
+        HSD_HIP_TRY(hipStreamSynchronize(st));
+    } else if (d->kind == HSD_RULE_EXPLICIT || d->kind == HSD_RULE_CUBE_TRAPEZOID) {
+        if (d->kind == HSD_RULE_EXPLICIT) {
+            if (d->n_nodes <= 0 || !d->nodes || !d->weights) {
+                set_error("explicit rule: empty or NULL arrays");
+                return HSD_EINVAL;
+            }
+            r->n_nodes = d->n_nodes;
+            r->host_nodes.assign(d->nodes, d->nodes + 3 * d->n_nodes);
+            r->host_weights.assign(d->weights, d->weights + d->n_nodes);
+            for (int64_t i = 0; i < 3 * d->n_nodes; ++i)
+                if (!std::isfinite(r->host_nodes[i])) { set_error("explicit rule: non-finite node"); return HSD_EINVAL; }
+            for (int64_t i = 0; i < d->n_nodes; ++i)
+                if (!std::isfinite(r->host_weights[i]) || r->host_weights[i] < 0) {
+                    set_error("explicit rule: weights must be finite and >= 0");
+                    return HSD_EINVAL;
+                }
+        } else {
+            if (!(d->xi_max > 0.0) || d->M <= 0 || d->M % 2) {
+                set_error("cube trapezoid rule: xi_max > 0 and even M > 0 required");
+                return HSD_EINVAL;
+            }
+            const int M = d->M;
+            const double h = 2.0 * d->xi_max / M;
+            const int64_t m1 = M + 1;
+            r->n_nodes = m1 * m1 * m1;
+            r->host_nodes.resize((size_t)r->n_nodes * 3);
+            r->host_weights.resize((size_t)r->n_nodes);
+            auto w1 = [&](int i) { return (i == 0 || i == M) ? 0.5 : 1.0; };
+            int64_t q = 0;
+            for (int i = 0; i <= M; ++i)
+                for (int j = 0; j <= M; ++j)
+                    for (int k = 0; k <= M; ++k, ++q) {
+                        r->host_nodes[3 * q] = (i - M / 2) * h;
+                        r->host_nodes[3 * q + 1] = (j - M / 2) * h;
+                        r->host_nodes[3 * q + 2] = (k - M / 2) * h;
+                        r->host_weights[q] = w1(i) * w1(j) * w1(k) * h * h * h;
+                    }
+        }
+        r->host_radii.resize((size_t)r->n_nodes);
+        for (int64_t i = 0; i < r->n_nodes; ++i) {
+            const double *x = &r->host_nodes[3 * i];
+            r->host_radii[i] = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        }
+        if ((stt = r->d_nodes.alloc(ctx, r->host_nodes.size() * 8)) != HSD_OK) return stt;
+        HSD_HIP_TRY(hipMemcpyAsync(r->d_nodes.ptr, r->host_nodes.data(), r->host_nodes.size() * 8, hipMemcpyHostToDevice, st));
+        HSD_HIP_TRY(hipStreamSynchronize(st));
+    } else {
+        set_error("unknown rule kind %d", d->kind);
+        return HSD_EINVAL;
+    }
+    *out = r.release();
+    return HSD_OK;
+}
+
+int64_t hsd_rule_num_nodes(const hsd_rule *r) { return r ? r->n_nodes : -1; }
+
+hsd_status hsd_rule_nodes(const hsd_rule *r, double *nodes, double *weights)
+{
+    if (!r) { set_error("rule is NULL"); return HSD_EINVAL; }
+    if (r->kind == HSD_RULE_SPHERICAL_PRODUCT) {
+        const auto &sp = r->sp;
+        for (int64_t d = 0; d < r->n_dir; ++d)
+            for (int64_t i = 0; i < r->n_rad; ++i) {
+                const int64_t q = d * r->n_rad + i;
+                const double rr = sp.radii[i];
+                if (nodes)
+                    for (int c = 0; c < 3; ++c) nodes[3 * q + c] = sp.dirs[3 * d + c] * rr;
+                if (weights) weights[q] = sp.wdir[d] * sp.wr[i] * rr * rr;
+            }
+    } else {
+        if (nodes) std::memcpy(nodes, r->host_nodes.data(), r->host_nodes.size() * 8);
+        if (weights) std::memcpy(weights, r->host_weights.data(), r->host_weights.size() * 8);
+    }
+    return HSD_OK;
+}
+
+void hsd_rule_destroy(hsd_rule *r)
+{
+    if (!r) return;
+    if (--r->refs > 0) return;
+    delete r;
+}
+
+hsd_status hsd_distance(hsd_ctx *ctx, const hsd_mesh *mu, const hsd_mesh *nu, const hsd_rule *rule,
+                        const hsd_params *p, hsd_result *out)
+{
+    hsd_status stt;
+    if ((stt = check_ctx(ctx)) != HSD_OK) return stt;
+    if (!mu || !rule || !out) { set_error("NULL argument"); return HSD_EINVAL; }
+    if ((stt = validate_params(p)) != HSD_OK) return stt;
+    if (nu && nu->ctx != ctx) { set_error("meshes belong to different contexts"); return HSD_EINVAL; }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t st = ctx->stream;
+    double pairs = 0.0;
+    double *d_res = nullptr;
+    HSD_HIP_TRY(hipEventRecord(ctx->ev0, st));
+    if ((stt = distance_core(ctx, st, mu, nu, rule, p, false, ctx->partial, ctx->nodebuf, ctx->redbuf,
+                             &d_res, &pairs, ctx->evt0, ctx->evt1)) != HSD_OK)
+        return stt;
+    HSD_HIP_TRY(hipEventRecord(ctx->ev1, st));
+    HSD_HIP_TRY(hipMemcpyAsync(ctx->host_result, d_res, sizeof(double), hipMemcpyDeviceToHost, st));
+    HSD_HIP_TRY(hipStreamSynchronize(st));
+    float ms = 0.0f, tms = 0.0f;
+    HSD_HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    HSD_HIP_TRY(hipEventElapsedTime(&tms, ctx->evt0, ctx->evt1));
+    std::memset(out, 0, sizeof *out);
+    out->d2 = ctx->host_result[0];
+    out->pairs = pairs;
+    out->device_ms = ms;
+    out->transform_ms = tms;
+    out->rel_err_stated = stated_rel_err(p, mu->nt + (nu ? nu->nt : 0));
+    out->status = HSD_OK;
+    return HSD_OK;
+}
+
+static hsd_status copy_out(void *dst, const void *src, size_t bytes, int32_t mem_kind, hipStream_t st)
+{
+    if (bytes == 0) return HSD_OK;
+    HSD_HIP_TRY(hipMemcpyAsync(dst, src, bytes,
+                               mem_kind == HSD_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    if (mem_kind != HSD_MEM_DEVICE) HSD_HIP_TRY(hipStreamSynchronize(st));
+    return HSD_OK;
+}
+
+hsd_status hsd_transform(hsd_ctx *ctx, const hsd_mesh *m, const double *nodes, int64_t n,
+                         int32_t nodes_mem_kind, const hsd_params *p, double *out_re_im,
+                         int32_t out_mem_kind)
+{
+    hsd_status stt;
+    if ((stt = check_ctx(ctx)) != HSD_OK) return stt;
+    if (!m || (n > 0 && (!nodes || !out_re_im))) { set_error("NULL argument"); return HSD_EINVAL; }
+    if (n < 0) { set_error("n < 0"); return HSD_EINVAL; }
+    if ((stt = validate_params(p)) != HSD_OK) return stt;
+    if (n == 0) return HSD_OK;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipStream_t st = ctx->stream;
+    // stage the nodes in nodebuf, partials in partial, result in redbuf
+    if ((stt = ctx->nodebuf.ensure(ctx, (size_t)n * 24)) != HSD_OK) return stt;
+    HSD_HIP_TRY(hipMemcpyAsync(ctx->nodebuf.buf.ptr, nodes, (size_t)n * 24,
+                               nodes_mem_kind == HSD_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+    std::vector<double> hn;
+    MeshPair mp;
+    mp.A = m->tris.as<const TriRec>();
+    mp.nA = m->nt;
+    const int K = choose_k_splits_gen(n, m->nt, ctx->num_cu, p->k_splits);
+    if ((stt = ctx->partial.ensure(ctx, (size_t)K * n * sizeof(double2))) != HSD_OK) return stt;
+    if ((stt = ctx->redbuf.ensure(ctx, (size_t)n * sizeof(double2))) != HSD_OK) return stt;
+    if (m->nt == 0) {
+        HSD_HIP_TRY(hipMemsetAsync(ctx->redbuf.buf.ptr, 0, (size_t)n * sizeof(double2), st));
+    } else {
+        if ((stt = launch_direct_gen(st, mp, ctx->nodebuf.buf.as<const double>(), n, p->form, p->taylor_tau, K,
+                                     ctx->partial.buf.as<double2>())) != HSD_OK)
+            return stt;
+        if ((stt = launch_sum_partials(st, ctx->partial.buf.as<const double2>(), K, n,
+                                       ctx->redbuf.buf.as<double2>())) != HSD_OK)
+            return stt;
+    }
+    return copy_out(out_re_im, ctx->redbuf.buf.ptr, (size_t)n * sizeof(double2), out_mem_kind, st);
+}
+
+hsd_status hsd_transform_rule(hsd_ctx *ctx, const hsd_mesh *m, const hsd_rule *rule_c,
+                              const hsd_params *p, double *out_re_im, int32_t out_mem_kind)
+{
+    hsd_status stt;
+    if ((stt = check_ctx(ctx)) != HSD_OK) return stt;
+    if (!m || !rule_c || !out_re_im) { set_error("NULL argument"); return HSD_EINVAL; }
+    if ((stt = validate_params(p)) != HSD_OK) return stt;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hsd_rule *rule = const_cast<hsd_rule *>(rule_c);
+    hipStream_t st = ctx->stream;
+    const int64_t N = rule->n_nodes;
+    if ((stt = ctx->redbuf.ensure(ctx, (size_t)N * sizeof(double2))) != HSD_OK) return stt;
+    double2 *res = ctx->redbuf.buf.as<double2>();
+    if (p->method == HSD_METHOD_NUFFT3) {
+        double pairs = 0;
+        if ((stt = nufft_transform_rule(ctx, st, m, nullptr, rule, p, res, &pairs)) != HSD_OK) return stt;
+    } else {
+        MeshPair mp;
+        mp.A = m->tris.as<const TriRec>();
+        mp.nA = m->nt;
+        int K = rule->kind == HSD_RULE_SPHERICAL_PRODUCT
+                    ? choose_k_splits_sp(rule, m->nt, p->form, ctx->num_cu, p->k_splits)
+                    : choose_k_splits_gen(N, m->nt, ctx->num_cu, p->k_splits);
+        if (m->nt == 0) {
+            HSD_HIP_TRY(hipMemsetAsync(res, 0, (size_t)N * sizeof(double2), st));
+        } else {
+            if ((stt = ctx->partial.ensure(ctx, (size_t)K * N * sizeof(double2))) != HSD_OK) return stt;
+            if (rule->kind == HSD_RULE_SPHERICAL_PRODUCT)
+                stt = launch_direct_sp(st, mp, rule, p->form, p->taylor_tau, K, ctx->partial.buf.as<double2>());
+            else
+                stt = launch_direct_gen(st, mp, rule->d_nodes.as<const double>(), N, p->form, p->taylor_tau, K,
+                                        ctx->partial.buf.as<double2>());
+            if (stt != HSD_OK) return stt;
+            if ((stt = launch_sum_partials(st, ctx->partial.buf.as<const double2>(), K, N, res)) != HSD_OK) return stt;
+        }
+    }
+    return copy_out(out_re_im, res, (size_t)N * sizeof(double2), out_mem_kind, st);
+}
+
+} // extern "C"

@@ -1,0 +1,184 @@
+// hsd_internal.hpp -- internal types shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hsd.h"
+
+namespace hsd {
+
+// One triangle as the affine image p0 + [e1 e2] u of the standard simplex
+// (eq. def_affine_simplex) with its area ratio J = |e1 x e2| (gamma in eq.
+// simplex32_ft).  80 bytes, read by whole wavefronts at once (scalar loads).
+struct TriRec {
+    double p0[3];
+    double e1[3];
+    double e2[3];
+    double J;
+};
+static_assert(sizeof(TriRec) == 80, "TriRec layout");
+
+void set_error(const char *fmt, ...);
+void ctx_retain(hsd_ctx *c);
+void ctx_release(hsd_ctx *c);
+std::string hip_msg(hipError_t e, const char *what);
+
+#define HSD_HIP_TRY(expr)                                                     \
+    do {                                                                      \
+        hipError_t _e = (expr);                                               \
+        if (_e != hipSuccess) {                                               \
+            ::hsd::set_error("%s", ::hsd::hip_msg(_e, #expr).c_str());       \
+            return HSD_EDEVICE;                                               \
+        }                                                                     \
+    } while (0)
+
+// Device allocation accounted against the context budget.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    hsd_ctx *ctx = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf();
+    hsd_status alloc(hsd_ctx *c, size_t n);
+    void release();
+    template <typename T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+// Reusable scratch (grows, never shrinks) owned by a context or a slot.
+struct Scratch {
+    DevBuf buf;
+    hsd_status ensure(hsd_ctx *c, size_t n);
+};
+
+} // namespace hsd
+
+struct hsd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    size_t budget = 0;
+    std::atomic<size_t> in_use{0};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evt0 = nullptr, evt1 = nullptr;
+    hsd::Scratch partial;     // [K][N] complex partial transforms
+    hsd::Scratch nodebuf;     // per-node residuals / finalize partials
+    hsd::Scratch redbuf;      // reduction partials + result
+    double *host_result = nullptr;   // pinned 8-byte readback
+    std::mutex mu;
+    int num_cu = 256;
+    std::atomic<int> refs{1};
+};
+
+struct hsd_mesh {
+    hsd_ctx *ctx = nullptr;
+    int64_t nv = 0, nt = 0;
+    hsd::DevBuf tris;         // TriRec[nt]
+    hsd::DevBuf verts;        // double[nv*3]
+    hsd::DevBuf idx;          // int32[nt*3]
+    hsd::DevBuf csr_ptr;      // int32[nv+1]   vertex -> (triangle, slot)
+    hsd::DevBuf csr_ent;      // int32[3*nt]   entries: 3*t + slot
+    std::vector<double> host_verts;
+    std::vector<int32_t> host_tris;
+    std::atomic<int> refs{1};
+    ~hsd_mesh();
+};
+
+namespace hsd {
+
+// Spherical product rule in factored form plus a flattened copy on demand.
+struct RuleSP {
+    double r_max = 0, delta = 0, h = 0;       // panel width, half width
+    int32_t P = 0, n = 0, n_cos = 0, n_phi = 0;
+    std::vector<double> x;                    // GL nodes on [-1, 1], ascending
+    std::vector<double> wx;                   // GL weights
+    std::vector<double> radii, wr;            // [P*n]
+    std::vector<double> mu, wmu;              // [n_cos]
+    std::vector<double> dirs;                 // [n_dir*3]
+    std::vector<double> wdir;                 // [n_dir]
+};
+
+} // namespace hsd
+
+struct hsd_rule {
+    hsd_ctx *ctx = nullptr;
+    int32_t kind = 0;
+    int64_t n_nodes = 0;
+    int64_t n_dir = 0, n_rad = 0;             // factored sizes (SP)
+    hsd::RuleSP sp;
+    std::vector<double> host_nodes;           // [n*3] flattened (all kinds)
+    std::vector<double> host_weights;         // [n]
+    std::vector<double> host_radii;           // [n]
+    hsd::DevBuf d_dirs;                       // SP: [n_dir*3]
+    hsd::DevBuf d_wdir;                       // SP: [n_dir]
+    hsd::DevBuf d_hx;                         // SP: h*x for the positive half [n/2]
+    hsd::DevBuf d_nodes;                      // EXPLICIT/CUBE: [n*3]
+    // per-s tables, kept for the rule's lifetime (requests with different s
+    // may run concurrently): SP -> radial [n_rad]; general -> per node [n]
+    struct Tables {
+        hsd::DevBuf w;                        // w (1+r^2)^-s (2pi)^-3 (SP: w_r r^2 ...)
+        hsd::DevBuf nu;                       // sphere transform 4 pi sin r / r
+    };
+    std::map<double, std::unique_ptr<Tables>> tabs;
+    std::mutex mu;
+    std::atomic<int> refs{1};
+    ~hsd_rule();
+};
+
+namespace hsd {
+
+// Launch-level description of one direct-sum evaluation.
+struct MeshPair {
+    const TriRec *A = nullptr; int64_t nA = 0;   // +1
+    const TriRec *B = nullptr; int64_t nB = 0;   // -1 (second mesh)
+};
+
+// Kernel launchers (hsd_direct.hip).
+hsd_status launch_direct_sp(hipStream_t st, const MeshPair &mp, const hsd_rule *rule,
+                            int form, double tau, int K, double2 *partial);
+hsd_status launch_direct_gen(hipStream_t st, const MeshPair &mp, const double *nodes,
+                             int64_t n, int form, double tau, int K, double2 *partial);
+hsd_status launch_finalize(hipStream_t st, const hsd_rule *rule, const double *wtab,
+                           const double *nutab, const double2 *partial, int K, int64_t n,
+                           bool sphere_target, double2 *resid_out, double *block_out,
+                           int64_t nblocks);
+hsd_status launch_final_reduce(hipStream_t st, const double *block_in, int64_t nblocks,
+                               double *out);
+hsd_status launch_sum_partials(hipStream_t st, const double2 *partial, int K, int64_t n,
+                               double2 *out);
+int64_t finalize_blocks(int64_t n);
+int choose_k_splits_sp(const hsd_rule *rule, int64_t nt, int form, int num_cu, int req);
+int choose_k_splits_gen(int64_t n, int64_t nt, int num_cu, int req);
+
+// Adjoint (hsd_adjoint.hip).
+hsd_status launch_adjoint(hipStream_t st, const hsd_mesh *m, const hsd_rule *rule,
+                          const double *wtab, const double2 *resid, int form, double tau,
+                          double *tri_grad /*[nt*9]*/);
+hsd_status launch_gather(hipStream_t st, const hsd_mesh *m, const double *tri_grad,
+                         double *grad);
+
+// NUFFT (hsd_nufft.hip).
+hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, const hsd_mesh *mu,
+                                const hsd_mesh *nu, const hsd_rule *rule,
+                                const hsd_params *p, double2 *out, double *pairs);
+
+// Shared host helpers (hsd_core.hip).
+hsd_status rule_tables(hsd_rule *rule, double s, hipStream_t st, const double **wtab,
+                       const double **nutab);
+hsd_status validate_params(const hsd_params *p);
+double stated_rel_err(const hsd_params *p, int64_t nt);
+hsd_status distance_core(hsd_ctx *ctx, hipStream_t st, const hsd_mesh *mu, const hsd_mesh *nu,
+                         const hsd_rule *rule, const hsd_params *p, bool keep_resid,
+                         Scratch &partial, Scratch &nodebuf, Scratch &redbuf,
+                         double **d_result, double *pairs, hipEvent_t ev_tb = nullptr,
+                         hipEvent_t ev_te = nullptr);
+
+} // namespace hsd

@@ -1,0 +1,189 @@
+// hsd_math.hpp -- device math for the MI355X direct-sum and NUFFT kernels.
+//
+// FP64 sine/cosine: Cody-Waite reduction by pi/2 (two-part constant, exact
+// FMA products) followed by the Maclaurin series of sin and cos on
+// [-pi/4, pi/4], truncated where the first omitted term is below 1e-19
+// (x^19/19! and x^20/20! at pi/4).  The coefficients are 1/k!, generated at
+// compile time; no tabulated constants beyond pi/2 itself.
+//
+// FP32 sine/cosine for the mixed form: the argument is reduced in FP64 to a
+// fraction of a revolution in [-1/2, 1/2] and handed to the hardware
+// transcendental unit (v_sin_f32 / v_cos_f32 take revolutions).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#define HSD_HD __host__ __device__ __forceinline__
+
+namespace hsd {
+
+// ---------------------------------------------------------------------------
+// compile-time 1/k!
+// ---------------------------------------------------------------------------
+constexpr double inv_factorial(int k)
+{
+    double f = 1.0;
+    for (int i = 2; i <= k; ++i) f *= (double)i;
+    return 1.0 / f;
+}
+
+// pi/2 split into the nearest double and the (rounded) remainder; 2/pi.
+constexpr double kPio2Hi = 1.5707963267948966;      // RN(pi/2)
+constexpr double kPio2Lo = 6.123233995736766e-17;   // RN(pi/2 - kPio2Hi)
+constexpr double kTwoOverPi = 0.6366197723675814;   // RN(2/pi)
+constexpr double kInvTwoPi = 0.15915494309189535;   // RN(1/(2 pi))
+constexpr double kPi = 3.141592653589793;
+constexpr double kFourPi = 12.566370614359172;
+
+// e^{-i theta} stored as (c, s) = (cos theta, sin theta).
+struct cs64 { double c, s; };
+struct cs32 { float c, s; };
+
+// sin and cos of x (|x| < 2^20 * pi/2), FP64, error ~1 ulp.
+HSD_HD cs64 sincos64(double x)
+{
+    const double q = __builtin_rint(x * kTwoOverPi);
+    double r = __builtin_fma(-q, kPio2Hi, x);
+    r = __builtin_fma(-q, kPio2Lo, r);
+    const int iq = (int)q;
+    const double r2 = r * r;
+    // sin r = r + r^3 * (-1/3! + r^2 (1/5! + r^2 (-1/7! + ...)))
+    double ps = inv_factorial(17);
+    ps = __builtin_fma(ps, r2, -inv_factorial(15));
+    ps = __builtin_fma(ps, r2, inv_factorial(13));
+    ps = __builtin_fma(ps, r2, -inv_factorial(11));
+    ps = __builtin_fma(ps, r2, inv_factorial(9));
+    ps = __builtin_fma(ps, r2, -inv_factorial(7));
+    ps = __builtin_fma(ps, r2, inv_factorial(5));
+    ps = __builtin_fma(ps, r2, -inv_factorial(3));
+    const double sn = __builtin_fma(ps * r2, r, r);
+    // cos r = 1 + r^2 * (-1/2! + r^2 (1/4! + r^2 (-1/6! + ...)))
+    double pc = -inv_factorial(18);
+    pc = __builtin_fma(pc, r2, inv_factorial(16));
+    pc = __builtin_fma(pc, r2, -inv_factorial(14));
+    pc = __builtin_fma(pc, r2, inv_factorial(12));
+    pc = __builtin_fma(pc, r2, -inv_factorial(10));
+    pc = __builtin_fma(pc, r2, inv_factorial(8));
+    pc = __builtin_fma(pc, r2, -inv_factorial(6));
+    pc = __builtin_fma(pc, r2, inv_factorial(4));
+    pc = __builtin_fma(pc, r2, -inv_factorial(2));
+    const double cn = __builtin_fma(pc, r2, 1.0);
+    // quadrant q mod 4: (sin, cos) of r + q pi/2
+    const bool swap = (iq & 1) != 0;
+    double s = swap ? cn : sn;
+    double c = swap ? sn : cn;
+    s = (iq & 2) ? -s : s;
+    c = ((iq + 1) & 2) ? -c : c;
+    return cs64{c, s};
+}
+
+// FP32 sin/cos of an FP32 angle in revolutions (|rev| <= 1/2 expected): the
+// hardware transcendental unit on the device; the host pass (used only by the
+// library's host-side self checks) evaluates the same quantity with libm.
+HSD_HD cs32 sincos32_rev(float rev)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return cs32{__builtin_amdgcn_cosf(rev), __builtin_amdgcn_sinf(rev)};
+#else
+    const double a = 6.283185307179586 * (double)rev;
+    return cs32{(float)std::cos(a), (float)std::sin(a)};
+#endif
+}
+
+// Hardware FP32 sin/cos of the angle x (radians) given in FP64: the angle is
+// reduced in FP64 to f = x/(2 pi) - rint(x/(2 pi)) in [-1/2, 1/2] and only
+// then rounded to FP32.
+HSD_HD cs32 sincos32_from64(double x)
+{
+    double p = x * kInvTwoPi;
+    double f = p - __builtin_rint(p);
+    float ff = (float)f;
+    return sincos32_rev(ff);
+}
+
+
+
+// 1/x for finite nonzero x: hardware estimate + two Newton steps (~1 ulp)
+// on the device; a correctly rounded division in the host pass.
+HSD_HD double rcp64(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    return y;
+#else
+    return 1.0 / x;
+#endif
+}
+
+HSD_HD float rcp32(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    float y = __builtin_amdgcn_rcpf(x);
+    float e = __builtin_fmaf(-x, y, 1.0f);
+    return __builtin_fmaf(y, e, y);
+#else
+    return 1.0f / x;
+#endif
+}
+
+// product of two unit phases e^{-i a} e^{-i b}
+HSD_HD cs64 pmul(cs64 a, cs64 b)
+{
+    return cs64{__builtin_fma(a.c, b.c, -a.s * b.s), __builtin_fma(a.s, b.c, a.c * b.s)};
+}
+// e^{-i a} e^{+i b}
+HSD_HD cs64 pmulc(cs64 a, cs64 b)
+{
+    return cs64{__builtin_fma(a.c, b.c, a.s * b.s), __builtin_fma(a.s, b.c, -a.c * b.s)};
+}
+HSD_HD cs32 pmul(cs32 a, cs32 b)
+{
+    return cs32{__builtin_fmaf(a.c, b.c, -a.s * b.s), __builtin_fmaf(a.s, b.c, a.c * b.s)};
+}
+HSD_HD cs32 pmulc(cs32 a, cs32 b)
+{
+    return cs32{__builtin_fmaf(a.c, b.c, a.s * b.s), __builtin_fmaf(a.s, b.c, -a.c * b.s)};
+}
+
+// Sorting network for three values: lo <= mid <= hi.
+template <typename T>
+HSD_HD void sort3(T x0, T x1, T x2, T &lo, T &mid, T &hi)
+{
+    T m1 = fmin(x0, x1), M1 = fmax(x0, x1);
+    T m2 = fmin(M1, x2);
+    hi = fmax(M1, x2);
+    lo = fmin(m1, m2);
+    mid = fmax(m1, m2);
+}
+
+// Power series of the second divided difference of exp at (i a, 0, -i b)
+// (a, b >= 0, a + b < tau <= 0.05): sum_n (-i)^n H_n / (n+2)!,
+// H_n = sum_{m<=n} (-a)^m b^(n-m).  Terms beyond n = 9 are below 1e-21.
+template <typename T>
+HSD_HD void dd2_series(T a, T b, T &re, T &im)
+{
+    const T na = -a;
+    T pw = na;
+    T H = b + na;                       // H_1
+    T sre = (T)0.5;                     // n = 0
+    T sim = -H * (T)inv_factorial(3);   // n = 1
+    pw *= na; H = H * b + pw; sre -= H * (T)inv_factorial(4);   // n = 2
+    pw *= na; H = H * b + pw; sim += H * (T)inv_factorial(5);   // n = 3
+    pw *= na; H = H * b + pw; sre += H * (T)inv_factorial(6);   // n = 4
+    pw *= na; H = H * b + pw; sim -= H * (T)inv_factorial(7);   // n = 5
+    pw *= na; H = H * b + pw; sre -= H * (T)inv_factorial(8);   // n = 6
+    pw *= na; H = H * b + pw; sim += H * (T)inv_factorial(9);   // n = 7
+    pw *= na; H = H * b + pw; sre += H * (T)inv_factorial(10);  // n = 8
+    pw *= na; H = H * b + pw; sim -= H * (T)inv_factorial(11);  // n = 9
+    re = sre;
+    im = sim;
+}
+
+} // namespace hsd

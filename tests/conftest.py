@@ -18,3 +18,19 @@ def orc():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session")
+def hsd_ctx():
+    """One device context for all GPU tests (skips when no GPU is visible)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2304_06340_amd as hsd
+    ctx = hsd.Context(0)
+    yield ctx
+    ctx.close()
+
+
+def golden_path(name):
+    return os.path.join(ROOT, "tests", "golden", name)

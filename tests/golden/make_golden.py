@@ -1,0 +1,82 @@
+"""Write the stored expected values used by the GPU parity tests.
+
+Calls only the CPU oracle (``oracle``) and the seeded input generators
+(``hsd_inputs``).  Usage:  python tests/golden/make_golden.py [name ...]
+Each fixture is an .npz/.json file next to this script; its header fields say
+what it is and how it was made.
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from hsd_inputs import icosphere  # noqa: E402
+
+# the configurations (rule parameters) the fixtures refer to
+RULE_SMALL = dict(r_max=64.0, n_panels=8, n_per_panel=16, n_cos=32, n_phi=64)      # 262,144 nodes
+RULE_LARGE = dict(r_max=256.0, n_panels=16, n_per_panel=16, n_cos=128, n_phi=256)  # 8,388,608 nodes
+
+
+def _rule(spec):
+    return oracle.spherical_product_rule(spec["r_max"], spec["n_panels"], spec["n_per_panel"],
+                                         spec["n_cos"], spec["n_phi"])
+
+
+def sampled(name, level, spec, n_samples=4096, seed=7):
+    """mu_h^ of the level-``level`` icosphere at ``n_samples`` seeded nodes of a rule."""
+    rule = _rule(spec)
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(len(rule), size=n_samples, replace=False))
+    v, f = icosphere(level)
+    t = time.time()
+    mu = oracle.transform(v, f, rule.nodes[idx])
+    dt = time.time() - t
+    np.savez(os.path.join(HERE, name + ".npz"), idx=idx, nodes=rule.nodes[idx], mu_re=mu.real,
+             mu_im=mu.imag, level=level, rule=json.dumps(spec),
+             note="oracle.transform at sampled rule nodes; written by make_golden.py")
+    print(f"{name}: {n_samples} nodes x {len(f)} triangles in {dt:.1f}s", flush=True)
+
+
+def d2_levels(name, levels, spec, s=1.0):
+    rule = _rule(spec)
+    out = {"rule": spec, "s": s, "d2": {}, "seconds": {},
+           "note": "oracle.distance vs the unit sphere; written by make_golden.py"}
+    path = os.path.join(HERE, name + ".json")
+    if os.path.exists(path):
+        old = json.load(open(path))
+        if old.get("rule") == spec:
+            out["d2"].update(old.get("d2", {}))
+            out["seconds"].update(old.get("seconds", {}))
+    for L in levels:
+        if str(L) in out["d2"]:
+            continue
+        v, f = icosphere(L)
+        t = time.time()
+        out["d2"][str(L)] = oracle.distance(v, f, rule, s=s)
+        out["seconds"][str(L)] = time.time() - t
+        print(f"{name}: level {L} d2={out['d2'][str(L)]!r} ({out['seconds'][str(L)]:.1f}s)", flush=True)
+        json.dump(out, open(path, "w"), indent=1)
+
+
+JOBS = {
+    "small_rule_levels": lambda: d2_levels("small_rule_levels", range(0, 6), RULE_SMALL),
+    "level7_small_rule_sampled": lambda: sampled("level7_small_rule_sampled", 7, RULE_SMALL),
+    "level7_large_rule_sampled": lambda: sampled("level7_large_rule_sampled", 7, RULE_LARGE),
+    "large_rule_level3": lambda: d2_levels("large_rule_levels", [3], RULE_LARGE),
+    "large_rule_level4": lambda: d2_levels("large_rule_levels", [3, 4], RULE_LARGE),
+    "small_rule_level7": lambda: d2_levels("small_rule_levels", [7], RULE_SMALL),
+}
+
+if __name__ == "__main__":
+    names = sys.argv[1:] or ["small_rule_levels", "level7_small_rule_sampled", "level7_large_rule_sampled"]
+    for n in names:
+        JOBS[n]()

@@ -1,0 +1,237 @@
+"""GPU parity of the direct-sum path against the FP64 oracle.
+
+Every test calls the HIP library through its C ABI (the Python binding only
+marshals arguments).  Bars: FP64 form within 1e-10 relative in d^2 and
+within ~1e-15 (1 + |xi|) * area per node in mu_h^; mixed form within its
+stated error.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import paper_2304_06340_amd as hsd
+from conftest import golden_path
+from hsd_inputs import (icosphere, perturb_harmonic, perturb_radial, random_rotation, rotate,
+                        random_triangles)
+
+pytestmark = pytest.mark.gpu
+
+SMALL = dict(r_max=64.0, n_panels=8, n_per_panel=16, n_cos=32, n_phi=64)
+
+
+def _rules(ctx, orc, spec):
+    g = hsd.Rule.spherical_product(ctx, spec["r_max"], spec["n_panels"], spec["n_per_panel"],
+                                   spec["n_cos"], spec["n_phi"])
+    o = orc.spherical_product_rule(spec["r_max"], spec["n_panels"], spec["n_per_panel"],
+                                   spec["n_cos"], spec["n_phi"])
+    return g, o
+
+
+def _area(v, f):
+    return 0.5 * np.linalg.norm(np.cross(v[f[:, 1]] - v[f[:, 0]], v[f[:, 2]] - v[f[:, 0]]), axis=1).sum()
+
+
+def _mu_tol(v, f, nodes, k=20.0, tau=1e-2):
+    """Per-node bound for two FP64 evaluations of mu_h^: phase rounding
+    (eps |xi|) plus the closed branch's eps/G error with G >= tau, times the
+    total J = 2 area."""
+    eps = 1.1e-16
+    A = max(_area(v, f), 1e-300)
+    return k * eps * (1.0 + np.linalg.norm(nodes, axis=1)) * A + 8.0 * eps / tau * A
+
+
+def test_rule_nodes_match_oracle_rule(hsd_ctx, orc):
+    g, o = _rules(hsd_ctx, orc, SMALL)
+    x, w = g.nodes()
+    assert x.shape == o.nodes.shape
+    assert np.max(np.abs(x - o.nodes)) <= 1e-13 * 64
+    assert np.max(np.abs(w - o.weights) / o.weights) <= 1e-12
+
+
+@pytest.mark.parametrize("spec", [
+    dict(r_max=64.0, n_panels=8, n_per_panel=16, n_cos=8, n_phi=16),     # 4 panels per lane group
+    dict(r_max=20.0, n_panels=6, n_per_panel=6, n_cos=5, n_phi=7),       # ragged lane count
+    dict(r_max=9.0, n_panels=3, n_per_panel=2, n_cos=3, n_phi=5),        # one panel per group
+    dict(r_max=40.0, n_panels=5, n_per_panel=10, n_cos=9, n_phi=11),
+])
+@pytest.mark.parametrize("form", ["fp64", "mixed"])
+def test_transform_on_rule_elementwise(hsd_ctx, orc, spec, form):
+    rng = np.random.default_rng(5)
+    v, f = icosphere(2)
+    v = rotate(perturb_radial(v, 0.01, rng), random_rotation(rng))
+    g, o = _rules(hsd_ctx, orc, spec)
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    got = hsd.transform_rule(hsd_ctx, mesh, g, hsd.Params(form=form))
+    ref = orc.transform(v, f, o.nodes)
+    err = np.abs(got - ref)
+    if form == "fp64":
+        assert np.all(err <= _mu_tol(v, f, o.nodes)), err.max()
+    else:
+        assert err.max() <= 2e-5 * _area(v, f), err.max()
+
+
+def test_general_kernel_special_cases(hsd_ctx, orc):
+    """Nodes along a face normal (all gaps 0), orthogonal to an edge (one gap
+    0), tiny |xi| (series branch), degenerate triangles, random nodes."""
+    rng = np.random.default_rng(8)
+    v, f = random_triangles(40, rng, scale=0.3)
+    # degenerate triangles: a repeated vertex and three collinear points
+    v = np.concatenate([v, [[0.1, 0.2, 0.3], [0.1, 0.2, 0.3], [0.5, 0.0, 0.0],
+                            [0.0, 0.0, 0.0], [1.0, 1.0, 1.0], [2.0, 2.0, 2.0]]])
+    f = np.concatenate([f, [[120, 121, 122], [123, 124, 125]]]).astype(np.int32)
+    p = v[f[0]]
+    nrm = np.cross(p[1] - p[0], p[2] - p[0])
+    nrm /= np.linalg.norm(nrm)
+    e1 = p[1] - p[0]
+    perp = np.cross(e1, nrm)
+    nodes = [nrm * 17.0, perp * 23.0, np.array([1e-9, 2e-9, -1e-9]), np.zeros(3)]
+    nodes += list(rng.normal(size=(300, 3)) * rng.choice([0.01, 1.0, 30.0, 200.0], size=(300, 1)))
+    nodes = np.array(nodes)
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    got = hsd.transform(hsd_ctx, mesh, nodes)
+    ref = orc.transform(v, f, nodes)
+    err = np.abs(got - ref)
+    assert np.all(err <= _mu_tol(v, f, nodes, 40.0)), err.max()
+    got_m = hsd.transform(hsd_ctx, mesh, nodes, hsd.Params(form="mixed"))
+    assert np.max(np.abs(got_m - ref)) <= 3e-6 * _area(v, f)
+
+
+def test_distance_small_rule_level2(hsd_ctx, orc):
+    v, f = icosphere(2)
+    g, o = _rules(hsd_ctx, orc, SMALL)
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    res = hsd.distance(hsd_ctx, mesh, None, g)
+    ref = orc.distance(v, f, o)
+    assert abs(res.d2 - ref) <= 1e-10 * ref, (res.d2, ref)
+    assert res.pairs == len(f) * len(o)
+
+
+def test_distance_levels_against_stored_oracle(hsd_ctx, orc):
+    path = golden_path("small_rule_levels.json")
+    if not os.path.exists(path):
+        pytest.skip("fixture not generated")
+    gold = json.load(open(path))
+    g = hsd.Rule.spherical_product(hsd_ctx, **{k: gold["rule"][k] for k in SMALL})
+    d = {}
+    for L, ref in sorted(gold["d2"].items(), key=lambda kv: int(kv[0])):
+        v, f = icosphere(int(L))
+        mesh = hsd.Mesh(hsd_ctx, v, f)
+        res = hsd.distance(hsd_ctx, mesh, None, g, hsd.Params(s=gold["s"]))
+        d[int(L)] = res.d2
+        print(f"level {L}: gpu {res.d2!r} oracle {ref!r} rel {abs(res.d2 - ref) / ref:.2e}")
+        assert abs(res.d2 - ref) <= 1e-10 * ref
+        mesh.close()
+    # quadratic convergence (Section 4.2): ratio of d = sqrt(d2) near 4
+    Ls = sorted(d)
+    ratios = [math.sqrt(d[a] / d[b]) for a, b in zip(Ls[:-1], Ls[1:]) if a >= 2]
+    assert all(3.8 < r < 4.2 for r in ratios), ratios
+
+
+@pytest.mark.parametrize("name,spec_key", [("level7_small_rule_sampled", "small"),
+                                           ("level7_large_rule_sampled", "large")])
+def test_level7_sampled_nodes(hsd_ctx, name, spec_key):
+    path = golden_path(name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip("fixture not generated")
+    z = np.load(path)
+    spec = json.loads(str(z["rule"]))
+    v, f = icosphere(int(z["level"]))
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    ref = z["mu_re"] + 1j * z["mu_im"]
+    nodes = z["nodes"]
+    got = hsd.transform(hsd_ctx, mesh, nodes)
+    err = np.abs(got - ref)
+    tol = _mu_tol(v, f, nodes, 20.0)
+    print(f"{name}: max err {err.max():.3e}, max err/tol {np.max(err / tol):.3f}")
+    assert np.all(err <= tol)
+    # the spherical-product kernel at the same rule nodes
+    g = hsd.Rule.spherical_product(hsd_ctx, **spec)
+    full = hsd.transform_rule(hsd_ctx, mesh, g)
+    err2 = np.abs(full[z["idx"]] - ref)
+    print(f"{name}: sp kernel max err {err2.max():.3e}")
+    assert np.all(err2 <= tol)
+
+
+def test_mesh_vs_mesh_and_empty(hsd_ctx, orc):
+    rng = np.random.default_rng(9)
+    spec = dict(r_max=24.0, n_panels=4, n_per_panel=8, n_cos=12, n_phi=16)
+    g, o = _rules(hsd_ctx, orc, spec)
+    v1, f1 = icosphere(2)
+    v2, f2 = icosphere(1)
+    v2 = rotate(v2, random_rotation(rng)) * 1.02
+    m1, m2 = hsd.Mesh(hsd_ctx, v1, f1), hsd.Mesh(hsd_ctx, v2, f2)
+    res = hsd.distance(hsd_ctx, m1, m2, g)
+    ref = orc.distance(v1, f1, o, verts2=v2, tris2=f2)
+    assert abs(res.d2 - ref) <= 1e-10 * ref
+    assert hsd.distance(hsd_ctx, m1, m1, g).d2 == pytest.approx(0.0, abs=1e-24)
+    empty = hsd.Mesh(hsd_ctx, np.zeros((0, 3)), np.zeros((0, 3), np.int32))
+    res0 = hsd.distance(hsd_ctx, empty, None, g)
+    ref0 = orc.distance(np.zeros((0, 3)), np.zeros((0, 3), np.int32), o)
+    assert res0.d2 == pytest.approx(ref0, rel=1e-13)
+
+
+def test_deterministic_and_split_invariant(hsd_ctx):
+    v, f = icosphere(3)
+    g = hsd.Rule.spherical_product(hsd_ctx, **SMALL)
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    for form in ("fp64", "mixed"):
+        a = hsd.distance(hsd_ctx, mesh, None, g, hsd.Params(form=form)).d2
+        b = hsd.distance(hsd_ctx, mesh, None, g, hsd.Params(form=form)).d2
+        assert a == b                      # bitwise run-to-run
+        for K in (1, 3, 16):
+            c = hsd.distance(hsd_ctx, mesh, None, g, hsd.Params(form=form, k_splits=K)).d2
+            assert abs(c - a) <= (1e-12 if form == "fp64" else 1e-6) * a
+
+
+def test_explicit_and_cube_rules(hsd_ctx, orc):
+    rng = np.random.default_rng(10)
+    v, f = icosphere(2)
+    v = perturb_harmonic(v, 0.05)
+    cube = hsd.Rule.cube_trapezoid(hsd_ctx, 5.0, 16)
+    oc = orc.cube_trapezoid_rule(5.0, 16)
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    for s in (1.0, 2.5):
+        res = hsd.distance(hsd_ctx, mesh, None, cube, hsd.Params(s=s))
+        ref = orc.distance(v, f, oc, s=s)
+        assert abs(res.d2 - ref) <= 1e-10 * ref
+    x = rng.normal(size=(1000, 3)) * 7
+    w = rng.uniform(0.1, 1.0, size=1000)
+    ex = hsd.Rule.explicit(hsd_ctx, x, w)
+    res = hsd.distance(hsd_ctx, mesh, None, ex)
+    ref = orc.distance(v, f, orc.Rule(x, w))
+    assert abs(res.d2 - ref) <= 1e-10 * ref
+
+
+def test_mixed_form_error_per_level(hsd_ctx):
+    g = hsd.Rule.spherical_product(hsd_ctx, **SMALL)
+    for L in range(2, 6):
+        v, f = icosphere(L)
+        mesh = hsd.Mesh(hsd_ctx, v, f)
+        a = hsd.distance(hsd_ctx, mesh, None, g).d2
+        r = hsd.distance(hsd_ctx, mesh, None, g, hsd.Params(form="mixed"))
+        rel = abs(r.d2 - a) / a
+        print(f"level {L}: mixed rel err vs fp64 {rel:.2e} (stated {r.rel_err_stated:.0e})")
+        assert rel <= r.rel_err_stated
+
+
+def test_invalid_inputs_are_rejected(hsd_ctx):
+    v, f = icosphere(1)
+    with pytest.raises(hsd.HsdError) as e:
+        hsd.Mesh(hsd_ctx, v, np.array([[0, 1, len(v)]], np.int32))
+    assert e.value.status == -1
+    bad = v.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(hsd.HsdError):
+        hsd.Mesh(hsd_ctx, bad, f)
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    g = hsd.Rule.spherical_product(hsd_ctx, 8.0, 2, 4, 4, 4)
+    for p in (hsd.Params(s=-1.0), hsd.Params(s=float("nan")), hsd.Params(taylor_tau=0.0)):
+        with pytest.raises(hsd.HsdError):
+            hsd.distance(hsd_ctx, mesh, None, g, p)
+    with pytest.raises(hsd.HsdError):
+        hsd.Rule.spherical_product(hsd_ctx, 8.0, 2, 5, 4, 4)   # odd nodes per panel
+    with pytest.raises(hsd.HsdError):
+        hsd.Rule.cube_trapezoid(hsd_ctx, 5.0, 7)

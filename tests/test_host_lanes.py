@@ -1,0 +1,137 @@
+"""CPU run of the HIP kernels' lane bodies against the oracle.
+
+The direct-sum kernels are thin wrappers around __host__ __device__ lane
+functions; libhsd exports a host-side driver of those functions (not part of
+the public ABI) so their arithmetic is checked here, on the CPU, before any
+GPU run.  The host pass differs from the device only in 1/x (IEEE division
+instead of the hardware estimate plus Newton steps) and, for the mixed form,
+in sin/cos of FP32 revolutions (libm instead of the transcendental unit).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+from hsd_inputs import icosphere, perturb_radial, random_rotation, rotate, random_triangles
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2304_06340_amd", "libhsd.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhsd.so not built")
+
+dp = C.POINTER(C.c_double)
+
+
+def _lib():
+    L = C.CDLL(LIB)
+    L.hsd__host_transform_sp.argtypes = [dp, C.c_void_p, C.c_int64, dp, C.c_int64, dp, C.c_int, C.c_int,
+                                         C.c_double, C.c_double, C.c_int, dp]
+    L.hsd__host_transform_gen.argtypes = [dp, C.c_void_p, C.c_int64, dp, C.c_int64, C.c_double, C.c_int, dp]
+    L.hsd__host_sincos64.argtypes = [dp, C.c_int64, dp, dp]
+    return L
+
+
+def _p(a):
+    return a.ctypes.data_as(dp)
+
+
+def host_sp(v, f, spec, form=0, tau=1e-2):
+    L = _lib()
+    P, n, nc, nphi, R = spec["n_panels"], spec["n_per_panel"], spec["n_cos"], spec["n_phi"], spec["r_max"]
+    x, _ = np.polynomial.legendre.leggauss(n)
+    mu, _ = np.polynomial.legendre.leggauss(nc)
+    phi = 2 * np.pi * np.arange(nphi) / nphi
+    st = np.sqrt(1 - mu * mu)
+    dirs = np.ascontiguousarray(np.stack([(st[:, None] * np.cos(phi)).ravel(),
+                                          (st[:, None] * np.sin(phi)).ravel(),
+                                          np.repeat(mu, nphi)], axis=1))
+    h = R / P / 2
+    hx = np.ascontiguousarray(h * x[n // 2:])
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.int32)
+    out = np.zeros(2 * len(dirs) * P * n)
+    L.hsd__host_transform_sp(_p(v), f.ctypes.data, len(f), _p(dirs), len(dirs), _p(hx), n, P, h, tau,
+                             form, _p(out))
+    return out[0::2] + 1j * out[1::2]
+
+
+def host_gen(v, f, nodes, form=0, tau=1e-2):
+    L = _lib()
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.int32)
+    x = np.ascontiguousarray(nodes, dtype=np.float64)
+    out = np.zeros(2 * len(x))
+    L.hsd__host_transform_gen(_p(v), f.ctypes.data, len(f), _p(x), len(x), tau, form, _p(out))
+    return out[0::2] + 1j * out[1::2]
+
+
+def _area(v, f):
+    return 0.5 * np.linalg.norm(np.cross(v[f[:, 1]] - v[f[:, 0]], v[f[:, 2]] - v[f[:, 0]]), axis=1).sum()
+
+
+def mu_tol(v, f, nodes, k=20.0, tau=1e-2):
+    """Per-node bound for two FP64 evaluations of mu_h^: phase rounding
+    (eps |xi| per vertex phase) plus the closed branch's eps/G error with
+    G >= tau, each times the triangle's J = 2 area."""
+    eps = 1.1e-16
+    A = _area(v, f)
+    return k * eps * (1.0 + np.linalg.norm(nodes, axis=1)) * A + 8.0 * eps / tau * A
+
+
+def test_sincos64_against_libm():
+    L = _lib()
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.uniform(-1, 1, 20000) * 10.0 ** rng.uniform(-8, 4, 20000),
+                        np.arange(-50, 51) * np.pi / 4, [0.0, -0.0, 1e-300]])
+    c = np.zeros_like(x)
+    s = np.zeros_like(x)
+    L.hsd__host_sincos64(_p(x), len(x), _p(c), _p(s))
+    tol = 2.5e-16 + 1.2e-16 * np.abs(x) * 1e-16 * 16
+    assert np.max(np.abs(c - np.cos(x)) - tol) <= 0
+    assert np.max(np.abs(s - np.sin(x)) - tol) <= 0
+
+
+@pytest.mark.parametrize("spec", [
+    dict(r_max=64.0, n_panels=8, n_per_panel=16, n_cos=4, n_phi=6),
+    dict(r_max=20.0, n_panels=6, n_per_panel=6, n_cos=5, n_phi=7),
+    dict(r_max=9.0, n_panels=3, n_per_panel=2, n_cos=3, n_phi=5),
+])
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("perturb", [True, False])
+def test_sp_lane_matches_oracle(orc, spec, form, perturb):
+    """perturb=False keeps the symmetric icosphere, whose edges are exactly
+    orthogonal to some rule directions (zero phase gaps)."""
+    rng = np.random.default_rng(5)
+    v, f = icosphere(1)
+    if perturb:
+        v = rotate(perturb_radial(v, 0.01, rng), random_rotation(rng))
+    got = host_sp(v, f, spec, form)
+    o = orc.spherical_product_rule(**spec)
+    ref = orc.transform(v, f, o.nodes)
+    err = np.abs(got - ref)
+    if form == 0:
+        assert np.all(err <= mu_tol(v, f, o.nodes)), err.max()
+    else:
+        assert np.all(np.isfinite(got))
+        assert err.max() <= 2e-5 * _area(v, f)
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_gen_lane_matches_oracle(orc, form):
+    rng = np.random.default_rng(8)
+    v, f = random_triangles(30, rng, scale=0.3)
+    v = np.concatenate([v, [[0.1, 0.2, 0.3], [0.1, 0.2, 0.3], [0.5, 0.0, 0.0]]])
+    f = np.concatenate([f, [[90, 91, 92]]]).astype(np.int32)
+    p = v[f[0]]
+    nrm = np.cross(p[1] - p[0], p[2] - p[0])
+    nrm /= np.linalg.norm(nrm)
+    perp = np.cross(p[1] - p[0], nrm)
+    nodes = np.array([nrm * 17.0, perp * 23.0, [1e-9, 2e-9, -1e-9], [0.0, 0.0, 0.0]]
+                     + list(rng.normal(size=(200, 3)) * rng.choice([0.01, 1.0, 30.0, 200.0], size=(200, 1))))
+    got = host_gen(v, f, nodes, form)
+    ref = orc.transform(v, f, nodes)
+    err = np.abs(got - ref)
+    if form == 0:
+        assert np.all(err <= mu_tol(v, f, nodes, 40.0)), err.max()
+    else:
+        assert err.max() <= 3e-6 * _area(v, f)
