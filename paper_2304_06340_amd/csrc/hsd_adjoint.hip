@@ -1,0 +1,305 @@
+// hsd_adjoint.hip -- gradient of d^2 with respect to the vertices of mu.
+//
+// With mu_T = J_T E_T, E_T = e[z0, z1, z2] (second divided difference of exp
+// at z_j = -i theta_j, theta_j = xi.v_j) and R_k = mu_h^(xi_k) - nu^(xi_k):
+//
+//   d(d^2)/dv_j(T) = sum_k 2 W_k Re( conj(R_k) dmu_T(xi_k)/dv_j )
+//                  = a_j S_E + J V_j,
+//   S_E = sum_k Re(q_k E_T(xi_k)),  V_j = sum_k Re(q_k D_j(xi_k)) xi_k,
+//
+// q_k = 2 W_k conj(R_k), a_j = dJ/dv_j = n_T x (v_{j+2} - v_{j+1}) and
+// D_j = dE/dtheta_j.  In the sorted frame E = exp(-i theta_mid) F(a, b) with
+// a = theta_mid - theta_lo, b = theta_hi - theta_mid:
+//   D_lo = -exp(-i theta_mid) F_a,  D_hi = exp(-i theta_mid) F_b,
+//   D_mid = -i E - D_lo - D_hi        (translation: sum_j D_j = -i E).
+// F, F_a, F_b come from the closed form (Y + iX)/G and its derivatives for
+// G >= tau, with series for sin(x)/x and (1-cos x)/x derivatives at small
+// arguments, and from the power series of the divided difference below tau.
+//
+// Work split: a lane owns one triangle; the 64 lanes of a wave walk the same
+// nodes (wave-uniform index, scalar loads of the direction, radius and
+// q_k); grid.y splits the directions.  Per-triangle partial sums [S][nt][10]
+// are combined in fixed order, turned into per-triangle vertex gradients,
+// and gathered to vertices through a vertex -> (triangle, slot) CSR in fixed
+// order.  No floating-point atomics.
+#include "hsd_internal.hpp"
+#include "hsd_math.hpp"
+
+namespace hsd {
+
+constexpr int kAdjNV = 10;   // S_E, V_0[3], V_1[3], V_2[3]
+
+// Maclaurin coefficients of the two derivatives:
+//   d/dx sin(x)/x       = sum_{k>=1} (-1)^k     2k     x^(2k-1) / (2k+1)!
+//   d/dx (1 - cos x)/x  = sum_{k>=1} (-1)^(k+1) (2k-1) x^(2k-2) / (2k)!
+constexpr double dsinc_coef(int k) { return ((k & 1) ? -1.0 : 1.0) * 2.0 * k * inv_factorial(2 * k + 1); }
+constexpr double dcosc_coef(int k) { return ((k & 1) ? 1.0 : -1.0) * (2.0 * k - 1.0) * inv_factorial(2 * k); }
+
+// d/dx sin(x)/x and d/dx (1-cos x)/x (x >= 0), with the series (k <= 8,
+// remainder < 1e-19) below 0.5.
+HSD_HD void dsinc_dcosc(double x, double sx, double cx, double &dsinc, double &dcosc)
+{
+    if (x < 0.5) {
+        const double x2 = x * x;
+        double ps = dsinc_coef(8), pc = dcosc_coef(8);
+#pragma unroll
+        for (int k = 7; k >= 1; --k) {
+            ps = __builtin_fma(ps, x2, dsinc_coef(k));
+            pc = __builtin_fma(pc, x2, dcosc_coef(k));
+        }
+        dsinc = ps * x;
+        dcosc = pc;
+    } else {
+        const double ix = 1.0 / x;
+        const double sinc = sx * ix, cosc = (1.0 - cx) * ix;
+        dsinc = (cx - sinc) * ix;
+        dcosc = (sx - cosc) * ix;
+    }
+}
+
+// F(a,b) = sum_n (-i)^n H_n/(n+2)! and its a- and b-derivatives, with
+// H_n = b H_{n-1} + (-a)^n, dH_n/da = b dH_{n-1}/da - n (-a)^{n-1},
+// dH_n/db = H_{n-1} + b dH_{n-1}/db.  Terms up to n = 12 (a + b < 0.05).
+HSD_HD void dd2_series_grad(double a, double b, double F[2], double Fa[2], double Fb[2])
+{
+    double H = 1.0, A = 0.0, B = 0.0, pw = 1.0;   // (-a)^n
+    double fr = 0.5, fi = 0.0, ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+#pragma unroll
+    for (int n = 1; n <= 12; ++n) {
+        const double pw_prev = pw;
+        pw *= -a;
+        const double Hprev = H;
+        H = b * H + pw;
+        A = b * A - (double)n * pw_prev;
+        B = Hprev + b * B;
+        const double c = inv_factorial(n + 2);
+        switch (n & 3) {   // (-i)^n = 1, -i, -1, i
+        case 0: fr += H * c; ar += A * c; br += B * c; break;
+        case 1: fi -= H * c; ai -= A * c; bi -= B * c; break;
+        case 2: fr -= H * c; ar -= A * c; br -= B * c; break;
+        default: fi += H * c; ai += A * c; bi += B * c; break;
+        }
+    }
+    F[0] = fr; F[1] = fi;
+    Fa[0] = ar; Fa[1] = ai;
+    Fb[0] = br; Fb[1] = bi;
+}
+
+// One (triangle, node) pair: E = exp(-i theta_mid) F and the three
+// derivatives D_lo, D_mid, D_hi (complex, in the sorted frame).
+HSD_HD void pair_grad(double thmid, double a, double b, double tau, double E[2], double Dlo[2],
+                      double Dmid[2], double Dhi[2])
+{
+    double F[2], Fa[2], Fb[2];
+    const double G = a + b;
+    if (G < tau) {
+        dd2_series_grad(a, b, F, Fa, Fb);
+    } else {
+        const cs64 hu = sincos64(0.5 * a), hv = sincos64(0.5 * b);
+        const double sa = 2.0 * hu.s * hu.c, ca = hu.c * hu.c - hu.s * hu.s;
+        const double sb = 2.0 * hv.s * hv.c, cb = hv.c * hv.c - hv.s * hv.s;
+        // sinc and (1-cos)/x of a, b (limits at 0)
+        const double sinc_a = a > 0.0 ? sa / a : 1.0;
+        const double sinc_b = b > 0.0 ? sb / b : 1.0;
+        const double cosc_a = a > 0.0 ? 2.0 * hu.s * hu.s / a : 0.0;
+        const double cosc_b = b > 0.0 ? 2.0 * hv.s * hv.s / b : 0.0;
+        double dsa, dca, dsb, dcb;
+        dsinc_dcosc(a, sa, ca, dsa, dca);
+        dsinc_dcosc(b, sb, cb, dsb, dcb);
+        const double iG = 1.0 / G;
+        F[0] = (cosc_b + cosc_a) * iG;
+        F[1] = (sinc_b - sinc_a) * iG;
+        Fa[0] = (dca - F[0]) * iG;
+        Fa[1] = (-dsa - F[1]) * iG;
+        Fb[0] = (dcb - F[0]) * iG;
+        Fb[1] = (dsb - F[1]) * iG;
+    }
+    const cs64 e1 = sincos64(thmid);   // exp(-i theta) = (c, -s)
+    const double er = e1.c, ei = -e1.s;
+    E[0] = er * F[0] - ei * F[1];
+    E[1] = er * F[1] + ei * F[0];
+    Dlo[0] = -(er * Fa[0] - ei * Fa[1]);
+    Dlo[1] = -(er * Fa[1] + ei * Fa[0]);
+    Dhi[0] = er * Fb[0] - ei * Fb[1];
+    Dhi[1] = er * Fb[1] + ei * Fb[0];
+    // -i E = (E_im, -E_re)
+    Dmid[0] = E[1] - Dlo[0] - Dhi[0];
+    Dmid[1] = -E[0] - Dlo[1] - Dhi[1];
+}
+
+// Lane body: one triangle against directions [d_begin, d_end) x all radii.
+// acc[10] = (S_E, V_0, V_1, V_2) for this slice.
+HSD_HD void adjoint_lane(const TriRec &T, const double *dirs, const double *radii, int n_rad,
+                         int64_t d_begin, int64_t d_end, const double2 *resid, const double *wdir,
+                         const double *wtab, double tau, double acc[kAdjNV])
+{
+    for (int i = 0; i < kAdjNV; ++i) acc[i] = 0.0;
+    for (int64_t d = d_begin; d < d_end; ++d) {
+        const double nx = dirs[3 * d], ny = dirs[3 * d + 1], nz = dirs[3 * d + 2];
+        const double t0 = nx * T.p0[0] + ny * T.p0[1] + nz * T.p0[2];
+        const double s1 = nx * T.e1[0] + ny * T.e1[1] + nz * T.e1[2];
+        const double s2 = nx * T.e2[0] + ny * T.e2[1] + nz * T.e2[2];
+        // sort (0, s1, s2) keeping the vertex index of each position
+        double v0 = 0.0, v1 = s1, v2 = s2;
+        int i0 = 0, i1 = 1, i2 = 2;
+        if (v1 < v0) { double t = v0; v0 = v1; v1 = t; int ti = i0; i0 = i1; i1 = ti; }
+        if (v2 < v1) { double t = v1; v1 = v2; v2 = t; int ti = i1; i1 = i2; i2 = ti; }
+        if (v1 < v0) { double t = v0; v0 = v1; v1 = t; int ti = i0; i0 = i1; i1 = ti; }
+        const double al = v1 - v0, be = v2 - v1, tmid = t0 + v1;
+        const double wd = wdir ? wdir[d] : 1.0;
+        double sE = 0.0, ulo = 0.0, umid = 0.0, uhi = 0.0;
+        for (int ir = 0; ir < n_rad; ++ir) {
+            const double r = radii[ir];
+            const int64_t node = d * n_rad + ir;
+            const double W = wd * wtab[wdir ? ir : node];
+            const double2 R = resid[node];
+            const double qr = 2.0 * W * R.x, qi = -2.0 * W * R.y;   // q = 2 W conj(R)
+            double E[2], Dlo[2], Dmid[2], Dhi[2];
+            pair_grad(r * tmid, r * al, r * be, tau, E, Dlo, Dmid, Dhi);
+            sE += qr * E[0] - qi * E[1];
+            ulo += r * (qr * Dlo[0] - qi * Dlo[1]);
+            umid += r * (qr * Dmid[0] - qi * Dmid[1]);
+            uhi += r * (qr * Dhi[0] - qi * Dhi[1]);
+        }
+        acc[0] += sE;
+        const double u[3] = {ulo, umid, uhi};
+        const int idx[3] = {i0, i1, i2};
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            const int j = idx[p];
+            // scatter by vertex index with selects (no dynamic register index)
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) {
+                const double w = (j == jj) ? u[p] : 0.0;
+                acc[1 + 3 * jj] += w * nx;
+                acc[2 + 3 * jj] += w * ny;
+                acc[3 + 3 * jj] += w * nz;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_adjoint(const TriRec *__restrict__ tris, int64_t nt,
+                                                 const double *__restrict__ dirs, int64_t n_dir,
+                                                 const double *__restrict__ radii, int n_rad,
+                                                 const double2 *__restrict__ resid,
+                                                 const double *__restrict__ wdir,
+                                                 const double *__restrict__ wtab, double tau,
+                                                 double *__restrict__ part)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int S = gridDim.y;
+    const int64_t d_begin = n_dir * blockIdx.y / S;
+    const int64_t d_end = n_dir * (blockIdx.y + 1) / S;
+    const TriRec T = tris[t < nt ? t : 0];
+    double acc[kAdjNV];
+    adjoint_lane(T, dirs, radii, n_rad, d_begin, d_end, resid, wdir, wtab, tau, acc);
+    if (t >= nt) return;
+    double *o = part + ((int64_t)blockIdx.y * nt + t) * kAdjNV;
+#pragma unroll
+    for (int i = 0; i < kAdjNV; ++i) o[i] = acc[i];
+}
+
+// Sum the S partials in fixed order and form g_j = a_j S_E + J V_j.
+__global__ void k_adjoint_finish(const TriRec *__restrict__ tris, int64_t nt, int S,
+                                 const double *__restrict__ part, double *__restrict__ tri_grad)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    double acc[kAdjNV];
+    for (int i = 0; i < kAdjNV; ++i) acc[i] = 0.0;
+    for (int s = 0; s < S; ++s)
+        for (int i = 0; i < kAdjNV; ++i) acc[i] += part[((int64_t)s * nt + t) * kAdjNV + i];
+    const TriRec T = tris[t];
+    const double e1[3] = {T.e1[0], T.e1[1], T.e1[2]}, e2[3] = {T.e2[0], T.e2[1], T.e2[2]};
+    double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double J = T.J;
+    const double iJ = J > 0.0 ? 1.0 / J : 0.0;
+    for (int c = 0; c < 3; ++c) n[c] *= iJ;
+    // edges opposite each vertex: v2 - v1 = e2 - e1, v0 - v2 = -e2, v1 - v0 = e1
+    const double opp[3][3] = {{e2[0] - e1[0], e2[1] - e1[1], e2[2] - e1[2]},
+                              {-e2[0], -e2[1], -e2[2]},
+                              {e1[0], e1[1], e1[2]}};
+    for (int j = 0; j < 3; ++j) {
+        const double *o = opp[j];
+        const double aj[3] = {n[1] * o[2] - n[2] * o[1], n[2] * o[0] - n[0] * o[2], n[0] * o[1] - n[1] * o[0]};
+        for (int c = 0; c < 3; ++c) tri_grad[t * 9 + 3 * j + c] = aj[c] * acc[0] + J * acc[1 + 3 * j + c];
+    }
+}
+
+// grad[v] = sum over CSR entries (3 t + slot), increasing t.
+__global__ void k_gather(int64_t nv, const int32_t *__restrict__ ptr, const int32_t *__restrict__ ent,
+                         const double *__restrict__ tri_grad, double *__restrict__ grad)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nv) return;
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int32_t e = ptr[v]; e < ptr[v + 1]; ++e) {
+        const int64_t ts = ent[e];   // 3 t + slot
+        const int64_t t = ts / 3, j = ts - 3 * t;
+        g0 += tri_grad[t * 9 + 3 * j];
+        g1 += tri_grad[t * 9 + 3 * j + 1];
+        g2 += tri_grad[t * 9 + 3 * j + 2];
+    }
+    grad[3 * v] = g0;
+    grad[3 * v + 1] = g1;
+    grad[3 * v + 2] = g2;
+}
+
+int adjoint_splits(int64_t nt, int64_t n_dir, int num_cu)
+{
+    const int64_t waves = ((nt + 255) / 256) * 4;
+    const int64_t target = (int64_t)num_cu * 4 * 8;
+    int64_t S = (target + waves - 1) / waves;
+    S = std::max<int64_t>(1, std::min<int64_t>(S, n_dir));
+    return (int)std::min<int64_t>(S, 65535);
+}
+
+hsd_status launch_adjoint_raw(hipStream_t st, const TriRec *tris, int64_t nt, const double *dirs, int64_t n_dir,
+                              const double *radii, int n_rad, const double2 *resid, const double *wdir,
+                              const double *wtab, double tau, int S, double *part, double *tri_grad)
+{
+    if (nt == 0) return HSD_OK;
+    const int64_t blocks = (nt + 255) / 256;
+    hipLaunchKernelGGL(k_adjoint, dim3((unsigned)blocks, (unsigned)S), dim3(256), 0, st, tris, nt, dirs, n_dir,
+                       radii, n_rad, resid, wdir, wtab, tau, part);
+    HSD_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_adjoint_finish, dim3((unsigned)blocks), dim3(256), 0, st, tris, nt, S, part, tri_grad);
+    HSD_HIP_TRY(hipGetLastError());
+    return HSD_OK;
+}
+
+hsd_status launch_gather(hipStream_t st, const hsd_mesh *m, const double *tri_grad, double *grad)
+{
+    if (m->nv == 0) return HSD_OK;
+    const int64_t blocks = (m->nv + 255) / 256;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)blocks), dim3(256), 0, st, m->nv, m->csr_ptr.as<const int32_t>(),
+                       m->csr_ent.as<const int32_t>(), tri_grad, grad);
+    HSD_HIP_TRY(hipGetLastError());
+    return HSD_OK;
+}
+
+} // namespace hsd
+
+using namespace hsd;
+
+extern "C" {
+
+// CPU run of the adjoint lane body for one triangle (self checks only):
+// acc[10] = (S_E, V_0, V_1, V_2) over all nodes.
+void hsd__host_adjoint_lane(const double *p0, const double *e1, const double *e2, double J, const double *dirs,
+                            int64_t n_dir, const double *radii, int n_rad, const double *resid,
+                            const double *wtab, double tau, double *acc)
+{
+    TriRec T;
+    for (int c = 0; c < 3; ++c) { T.p0[c] = p0[c]; T.e1[c] = e1[c]; T.e2[c] = e2[c]; }
+    T.J = J;
+    adjoint_lane(T, dirs, radii, n_rad, 0, n_dir, (const double2 *)resid, nullptr, wtab, tau, acc);
+}
+
+void hsd__host_pair_grad(double thmid, double a, double b, double tau, double *out /*8*/)
+{
+    pair_grad(thmid, a, b, tau, out, out + 2, out + 4, out + 6);
+}
+
+} // extern "C"

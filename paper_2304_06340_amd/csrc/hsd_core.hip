@@ -206,8 +206,8 @@ hsd_status rule_tables(hsd_rule *rule, double s, hipStream_t st, const double **
 // nodebuf (double2[N]) for the adjoint.
 hsd_status distance_core(hsd_ctx *ctx, hipStream_t st, const hsd_mesh *mu, const hsd_mesh *nu,
                          const hsd_rule *rule_c, const hsd_params *p, bool keep_resid,
-                         Scratch &partial, Scratch &nodebuf, Scratch &redbuf, double **d_result,
-                         double *pairs, hipEvent_t ev_tb, hipEvent_t ev_te)
+                         Scratch &partial, Scratch &nodebuf, Scratch &redbuf, NufftScratch &nsc,
+                         double **d_result, double *pairs, hipEvent_t ev_tb, hipEvent_t ev_te)
 {
     hsd_rule *rule = const_cast<hsd_rule *>(rule_c);
     hsd_status stt;
@@ -227,7 +227,7 @@ hsd_status distance_core(hsd_ctx *ctx, hipStream_t st, const hsd_mesh *mu, const
     if (ev_tb) HSD_HIP_TRY(hipEventRecord(ev_tb, st));
     if (p->method == HSD_METHOD_NUFFT3) {
         if ((stt = partial.ensure(ctx, (size_t)N * sizeof(double2))) != HSD_OK) return stt;
-        if ((stt = nufft_transform_rule(ctx, st, mu, nu, rule, p, partial.buf.as<double2>(), pairs)) != HSD_OK)
+        if ((stt = nufft_transform_rule(ctx, st, nsc, mu, nu, rule, p, partial.buf.as<double2>(), pairs)) != HSD_OK)
             return stt;
         mu_hat = partial.buf.as<const double2>();
     } else {
@@ -299,6 +299,7 @@ void ctx_release(hsd_ctx *c)
     c->partial.buf.release();
     c->nodebuf.buf.release();
     c->redbuf.buf.release();
+    c->gradbuf.buf.release();
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->evt0) (void)hipEventDestroy(c->evt0);
@@ -343,6 +344,7 @@ hsd_rule::~hsd_rule()
     d_dirs.release();
     d_wdir.release();
     d_hx.release();
+    d_radii.release();
     d_nodes.release();
     tabs.clear();
     ctx_release(c);
@@ -558,6 +560,8 @@ hsd_status hsd_freq_rule(hsd_ctx *ctx, const hsd_rule_desc *d, hsd_rule **out)
         HSD_HIP_TRY(hipMemcpyAsync(r->d_dirs.ptr, sp.dirs.data(), sp.dirs.size() * 8, hipMemcpyHostToDevice, st));
         HSD_HIP_TRY(hipMemcpyAsync(r->d_wdir.ptr, sp.wdir.data(), sp.wdir.size() * 8, hipMemcpyHostToDevice, st));
         HSD_HIP_TRY(hipMemcpyAsync(r->d_hx.ptr, hx.data(), hx.size() * 8, hipMemcpyHostToDevice, st));
+        if ((stt = r->d_radii.alloc(ctx, sp.radii.size() * 8)) != HSD_OK) return stt;
+        HSD_HIP_TRY(hipMemcpyAsync(r->d_radii.ptr, sp.radii.data(), sp.radii.size() * 8, hipMemcpyHostToDevice, st));
         HSD_HIP_TRY(hipStreamSynchronize(st));
     } else if (d->kind == HSD_RULE_EXPLICIT || d->kind == HSD_RULE_CUBE_TRAPEZOID) {
         if (d->kind == HSD_RULE_EXPLICIT) {
@@ -604,6 +608,9 @@ hsd_status hsd_freq_rule(hsd_ctx *ctx, const hsd_rule_desc *d, hsd_rule **out)
         }
         if ((stt = r->d_nodes.alloc(ctx, r->host_nodes.size() * 8)) != HSD_OK) return stt;
         HSD_HIP_TRY(hipMemcpyAsync(r->d_nodes.ptr, r->host_nodes.data(), r->host_nodes.size() * 8, hipMemcpyHostToDevice, st));
+        static const double one = 1.0;
+        if ((stt = r->d_radii.alloc(ctx, 8)) != HSD_OK) return stt;
+        HSD_HIP_TRY(hipMemcpyAsync(r->d_radii.ptr, &one, 8, hipMemcpyHostToDevice, st));
         HSD_HIP_TRY(hipStreamSynchronize(st));
     } else {
         set_error("unknown rule kind %d", d->kind);
@@ -656,7 +663,7 @@ hsd_status hsd_distance(hsd_ctx *ctx, const hsd_mesh *mu, const hsd_mesh *nu, co
     double *d_res = nullptr;
     HSD_HIP_TRY(hipEventRecord(ctx->ev0, st));
     if ((stt = distance_core(ctx, st, mu, nu, rule, p, false, ctx->partial, ctx->nodebuf, ctx->redbuf,
-                             &d_res, &pairs, ctx->evt0, ctx->evt1)) != HSD_OK)
+                             ctx->nufft, &d_res, &pairs, ctx->evt0, ctx->evt1)) != HSD_OK)
         return stt;
     HSD_HIP_TRY(hipEventRecord(ctx->ev1, st));
     HSD_HIP_TRY(hipMemcpyAsync(ctx->host_result, d_res, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -671,6 +678,65 @@ hsd_status hsd_distance(hsd_ctx *ctx, const hsd_mesh *mu, const hsd_mesh *nu, co
     out->transform_ms = tms;
     out->rel_err_stated = stated_rel_err(p, mu->nt + (nu ? nu->nt : 0));
     out->status = HSD_OK;
+    return HSD_OK;
+}
+
+hsd_status hsd_distance_grad(hsd_ctx *ctx, const hsd_mesh *mu, const hsd_mesh *nu, const hsd_rule *rule_c,
+                             const hsd_params *p, double *grad, int32_t mem_kind, hsd_result *out)
+{
+    hsd_status stt;
+    if ((stt = check_ctx(ctx)) != HSD_OK) return stt;
+    if (!mu || !rule_c || !out || (mu->nv > 0 && !grad)) { set_error("NULL argument"); return HSD_EINVAL; }
+    if ((stt = validate_params(p)) != HSD_OK) return stt;
+    if (p->method != HSD_METHOD_DIRECT) {
+        set_error("hsd_distance_grad supports the direct method only");
+        return HSD_EINVAL;
+    }
+    if (mem_kind != HSD_MEM_HOST && mem_kind != HSD_MEM_DEVICE) { set_error("bad mem_kind"); return HSD_EINVAL; }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hsd_rule *rule = const_cast<hsd_rule *>(rule_c);
+    hipStream_t st = ctx->stream;
+    double pairs = 0.0;
+    double *d_res = nullptr;
+    HSD_HIP_TRY(hipEventRecord(ctx->ev0, st));
+    // forward pass, keeping R_k (nodebuf)
+    if ((stt = distance_core(ctx, st, mu, nu, rule, p, true, ctx->partial, ctx->nodebuf, ctx->redbuf, ctx->nufft,
+                             &d_res, &pairs, ctx->evt0, ctx->evt1)) != HSD_OK)
+        return stt;
+    const double *wtab = nullptr, *nutab = nullptr;
+    if ((stt = rule_tables(rule, p->s, st, &wtab, &nutab)) != HSD_OK) return stt;
+    const bool sp = rule->kind == HSD_RULE_SPHERICAL_PRODUCT;
+    const int64_t n_dir = sp ? rule->n_dir : rule->n_nodes;
+    const int n_rad = sp ? (int)rule->n_rad : 1;
+    const double *dirs = sp ? rule->d_dirs.as<const double>() : rule->d_nodes.as<const double>();
+    const int S = adjoint_splits(mu->nt, n_dir, ctx->num_cu);
+    const size_t tri_bytes = (size_t)mu->nt * 9 * 8, vert_bytes = (size_t)mu->nv * 3 * 8;
+    if ((stt = ctx->partial.ensure(ctx, std::max<size_t>((size_t)S * mu->nt * 10 * 8, 8))) != HSD_OK) return stt;
+    if ((stt = ctx->gradbuf.ensure(ctx, tri_bytes + vert_bytes + 8)) != HSD_OK) return stt;
+    double *tri_grad = ctx->gradbuf.buf.as<double>();
+    double *vgrad = tri_grad + (size_t)mu->nt * 9;
+    // the (2pi)^-3 w (1+r^2)^-s weights: SP -> wdir x radial table
+    if ((stt = launch_adjoint_raw(st, mu->tris.as<const TriRec>(), mu->nt, dirs, n_dir,
+                                  rule->d_radii.as<const double>(), n_rad, ctx->nodebuf.buf.as<const double2>(),
+                                  sp ? rule->d_wdir.as<const double>() : nullptr, wtab, p->taylor_tau, S,
+                                  ctx->partial.buf.as<double>(), tri_grad)) != HSD_OK)
+        return stt;
+    if ((stt = launch_gather(st, mu, tri_grad, vgrad)) != HSD_OK) return stt;
+    HSD_HIP_TRY(hipEventRecord(ctx->ev1, st));
+    HSD_HIP_TRY(hipMemcpyAsync(ctx->host_result, d_res, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (mu->nv > 0)
+        HSD_HIP_TRY(hipMemcpyAsync(grad, vgrad, vert_bytes,
+                                   mem_kind == HSD_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    HSD_HIP_TRY(hipStreamSynchronize(st));
+    float ms = 0.0f, tms = 0.0f;
+    HSD_HIP_TRY(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    HSD_HIP_TRY(hipEventElapsedTime(&tms, ctx->evt0, ctx->evt1));
+    std::memset(out, 0, sizeof *out);
+    out->d2 = ctx->host_result[0];
+    out->pairs = pairs;
+    out->device_ms = ms;
+    out->transform_ms = tms;
+    out->rel_err_stated = stated_rel_err(p, mu->nt + (nu ? nu->nt : 0));
     return HSD_OK;
 }
 
@@ -734,7 +800,7 @@ hsd_status hsd_transform_rule(hsd_ctx *ctx, const hsd_mesh *m, const hsd_rule *r
     double2 *res = ctx->redbuf.buf.as<double2>();
     if (p->method == HSD_METHOD_NUFFT3) {
         double pairs = 0;
-        if ((stt = nufft_transform_rule(ctx, st, m, nullptr, rule, p, res, &pairs)) != HSD_OK) return stt;
+        if ((stt = nufft_transform_rule(ctx, st, ctx->nufft, m, nullptr, rule, p, res, &pairs)) != HSD_OK) return stt;
     } else {
         MeshPair mp;
         mp.A = m->tris.as<const TriRec>();

@@ -147,7 +147,7 @@ HSD_HD void sp_lane_f64(const TriRec *A, int64_t nA, const TriRec *B, int64_t t_
 }
 
 // Spherical-product lane, mixed precision: FP64 geometry, gaps, phase
-// constants and their reduction mod 2 pi; FP32 sin/cos of the reduced phases,
+// constants and their reduction mod pi/2; FP32 sin/cos of the reduced phases,
 // FP32 per-node products and tile sums; FP64 running totals; series branch
 // in FP64.  Same slot layout as sp_lane_f64.
 template <int PG>
@@ -189,9 +189,9 @@ HSD_HD void sp_lane_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t 
             cs32 Bk[3], S[3], Cp[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                Bk[c] = sincos32_from64(hx * fr[c]);
-                S[c] = sincos32_from64(2.0 * h * fr[c]);
-                Cp[c] = sincos32_from64((double)(2 * p0 + 1) * h * fr[c]);
+                Bk[c] = sincos32_acc(hx * fr[c]);
+                S[c] = sincos32_acc(2.0 * h * fr[c]);
+                Cp[c] = sincos32_acc((double)(2 * p0 + 1) * h * fr[c]);
             }
 #pragma unroll
             for (int pl = 0; pl < PG; ++pl) {
@@ -201,9 +201,9 @@ HSD_HD void sp_lane_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t 
                     cs32 E1, Eu, Ev;
                     if (sg == 1 && p0 + pl == 0) {
                         const double rd = h - hx;   // small radius: direct phases
-                        E1 = sincos32_from64(rd * fr[0]);
-                        Eu = sincos32_from64(rd * fr[1]);
-                        Ev = sincos32_from64(rd * fr[2]);
+                        E1 = sincos32_acc(rd * fr[0]);
+                        Eu = sincos32_acc(rd * fr[1]);
+                        Ev = sincos32_acc(rd * fr[2]);
                     } else {
                         E1 = sg == 0 ? pmul(Cp[0], Bk[0]) : pmulc(Cp[0], Bk[0]);
                         Eu = sg == 0 ? pmul(Cp[1], Bk[1]) : pmulc(Cp[1], Bk[1]);
@@ -297,7 +297,7 @@ HSD_HD void gen_node_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t
             double lo, mid, hi;
             sort3(0.0, d1, d2, lo, mid, hi);
             const double a = mid - lo, b = hi - mid;
-            const cs32 E1 = sincos32_from64(t0 + mid);
+            const cs32 E1 = sincos32_acc(t0 + mid);
             float Yr, Xr;
             if (a + b < fmax(tau, kMixedTau)) {
                 double fre, fim;
@@ -309,8 +309,8 @@ HSD_HD void gen_node_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t
                 const double iG = rcp64(ac + bc);
                 const float Ka = (float)(2.0 * J * rcp64(ac) * iG);
                 const float Kb = (float)(2.0 * J * rcp64(bc) * iG);
-                const cs32 Eu = sincos32_from64(0.5 * ac);
-                const cs32 Ev = sincos32_from64(0.5 * bc);
+                const cs32 Eu = sincos32_acc(0.5 * ac);
+                const cs32 Ev = sincos32_acc(0.5 * bc);
                 const float Pv = Kb * Ev.s, Pu = Ka * Eu.s;
                 Yr = __builtin_fmaf(Pv, Ev.s, Pu * Eu.s);
                 Xr = __builtin_fmaf(Pv, Ev.c, -Pu * Eu.c);

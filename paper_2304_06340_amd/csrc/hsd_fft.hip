@@ -1,0 +1,238 @@
+// hsd_fft.hip -- cubic 3-D complex FFT (FP64), sizes n = 2^a 3^b <= 2048,
+// forward sign: X_m = sum_l x_l exp(-2 pi i l m / n), unnormalised.
+//
+// One kernel per axis.  A block loads Bt whole 1-D lines of the axis into
+// LDS (for the strided axes the Bt lines are consecutive in the contiguous
+// dimension, so every global access is a coalesced run of Bt complex
+// values), runs a Stockham autosort FFT in LDS (radix 4, 3 and 2 stages;
+// each stage reads its inputs to registers, synchronises, and writes its
+// outputs in place), and writes the lines back.  Twiddles come from a table
+// exp(-2 pi i k / n), k < n, built on the host in FP64.
+#include <vector>
+
+#include "hsd_internal.hpp"
+#include "hsd_math.hpp"
+#include "hsd_fft.hpp"
+
+namespace hsd {
+
+constexpr int kFftThreads = 256;
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+constexpr int kFftMaxElems = 4096;   // complex values per block tile (64 KB of LDS)
+
+// One Stockham stage of radix R on Bt lines of length n in LDS: every
+// thread first gathers (and twiddles) the inputs of all its butterflies into
+// registers, the block synchronises, then the outputs are written in place.
+template <int R>
+__device__ void stockham_stage(double2 *buf, int n, int Bt, int Ns, const double2 *__restrict__ tw)
+{
+    constexpr int kMaxBf = (kFftMaxElems / R + kFftThreads - 1) / kFftThreads;
+    const int nb = n / R;              // butterflies per line
+    const int total = nb * Bt;
+    const int twstep = n / (Ns * R);   // exp(-2 pi i / (Ns R)) = tw[twstep]
+    double2 x[kMaxBf][R];
+#pragma unroll
+    for (int b = 0; b < kMaxBf; ++b) {
+        const int idx = b * kFftThreads + (int)threadIdx.x;
+        if (idx < total) {
+            const int line = idx / nb;
+            const int j = idx - line * nb;
+            const double2 *L = buf + (size_t)line * n;
+            const int k = j % Ns;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                double2 a = L[j + r * nb];
+                if (r > 0) a = cmul(a, tw[r * k * twstep]);
+                x[b][r] = a;
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < kMaxBf; ++b) {
+        const int idx = b * kFftThreads + (int)threadIdx.x;
+        if (idx < total) {
+            const int line = idx / nb;
+            const int j = idx - line * nb;
+            const double2 *xi = x[b];
+            double2 y[R];
+            if (R == 2) {
+                y[0] = make_double2(xi[0].x + xi[1].x, xi[0].y + xi[1].y);
+                y[1] = make_double2(xi[0].x - xi[1].x, xi[0].y - xi[1].y);
+            } else if (R == 3) {
+                // exp(-2 pi i / 3) = -1/2 - i sqrt(3)/2
+                const double c = -0.5, s = 0.86602540378443864676;
+                const double2 t = make_double2(xi[1].x + xi[2].x, xi[1].y + xi[2].y);
+                const double2 d = make_double2(xi[1].x - xi[2].x, xi[1].y - xi[2].y);
+                y[0] = make_double2(xi[0].x + t.x, xi[0].y + t.y);
+                const double2 m = make_double2(xi[0].x + c * t.x, xi[0].y + c * t.y);
+                // -i s d = (s d.y, -s d.x)
+                y[1] = make_double2(m.x + s * d.y, m.y - s * d.x);
+                y[2] = make_double2(m.x - s * d.y, m.y + s * d.x);
+            } else {   // R == 4
+                const double2 a0 = make_double2(xi[0].x + xi[2].x, xi[0].y + xi[2].y);
+                const double2 a1 = make_double2(xi[0].x - xi[2].x, xi[0].y - xi[2].y);
+                const double2 b0 = make_double2(xi[1].x + xi[3].x, xi[1].y + xi[3].y);
+                const double2 b1 = make_double2(xi[1].x - xi[3].x, xi[1].y - xi[3].y);
+                y[0] = make_double2(a0.x + b0.x, a0.y + b0.y);
+                y[2] = make_double2(a0.x - b0.x, a0.y - b0.y);
+                // -i b1 = (b1.y, -b1.x)
+                y[1] = make_double2(a1.x + b1.y, a1.y - b1.x);
+                y[3] = make_double2(a1.x - b1.y, a1.y + b1.x);
+            }
+            double2 *L = buf + (size_t)line * n;
+            const int k = j % Ns;
+            const int obase = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int q = 0; q < R; ++q) L[obase + q * Ns] = y[q];
+        }
+    }
+    __syncthreads();
+}
+
+// Batched 1-D FFTs along one axis.  Line (o, i) element e lives at
+// data[o * so + i * si + e * se]; blockIdx.x covers Bt consecutive i for
+// one o = blockIdx.y.
+__global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *__restrict__ data, int n, int Bt, int64_t se,
+                                                          int64_t si, int64_t so, int64_t n_inner,
+                                                          const double2 *__restrict__ tw, const int *__restrict__ plan,
+                                                          int n_stages)
+{
+    extern __shared__ double2 lds[];
+    const int64_t i0 = (int64_t)blockIdx.x * Bt;
+    const int64_t o = blockIdx.y;
+    const int nl = (int)((n_inner - i0) < Bt ? (n_inner - i0) : Bt);
+    double2 *base = data + o * so;
+    const int total = nl * n;
+    // load
+    for (int idx = threadIdx.x; idx < total; idx += kFftThreads) {
+        int line, e;
+        if (se == 1) { line = idx / n; e = idx - line * n; }
+        else { e = idx / nl; line = idx - e * nl; }
+        lds[(size_t)line * n + e] = base[(i0 + line) * si + (int64_t)e * se];
+    }
+    __syncthreads();
+    int Ns = 1;
+    for (int s = 0; s < n_stages; ++s) {
+        const int R = plan[s];
+        if (R == 4) stockham_stage<4>(lds, n, nl, Ns, tw);
+        else if (R == 3) stockham_stage<3>(lds, n, nl, Ns, tw);
+        else stockham_stage<2>(lds, n, nl, Ns, tw);
+        Ns *= R;
+    }
+    // store
+    for (int idx = threadIdx.x; idx < total; idx += kFftThreads) {
+        int line, e;
+        if (se == 1) { line = idx / n; e = idx - line * n; }
+        else { e = idx / nl; line = idx - e * nl; }
+        base[(i0 + line) * si + (int64_t)e * se] = lds[(size_t)line * n + e];
+    }
+}
+
+bool fft_size_ok(int n)
+{
+    if (n < 1 || n > 2048) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+int fft_next_size(int n)
+{
+    for (int m = std::max(n, 1);; ++m)
+        if (fft_size_ok(m)) return m;
+}
+
+hsd_status FftPlan::init(hsd_ctx *ctx, int n_)
+{
+    if (!fft_size_ok(n_)) {
+        set_error("FFT size %d is not 2^a 3^b <= 2048", n_);
+        return HSD_EINVAL;
+    }
+    n = n_;
+    std::vector<int> st;
+    int m = n;
+    while (m % 4 == 0) { st.push_back(4); m /= 4; }
+    while (m % 3 == 0) { st.push_back(3); m /= 3; }
+    while (m % 2 == 0) { st.push_back(2); m /= 2; }
+    stages = st;
+    std::vector<double2> t((size_t)n);
+    for (int k = 0; k < n; ++k) {
+        const long double a = 2.0L * 3.141592653589793238462643383279503L * (long double)k / (long double)n;
+        t[k] = make_double2((double)std::cos(a), (double)-std::sin(a));
+    }
+    hsd_status stt;
+    if ((stt = tw.alloc(ctx, (size_t)n * sizeof(double2))) != HSD_OK) return stt;
+    if ((stt = plan.alloc(ctx, std::max<size_t>(st.size(), 1) * sizeof(int))) != HSD_OK) return stt;
+    HSD_HIP_TRY(hipMemcpy(tw.ptr, t.data(), (size_t)n * sizeof(double2), hipMemcpyHostToDevice));
+    if (!st.empty()) HSD_HIP_TRY(hipMemcpy(plan.ptr, st.data(), st.size() * sizeof(int), hipMemcpyHostToDevice));
+    return HSD_OK;
+}
+
+// Lines per block: keep the LDS tile within kFftMaxElems complex values.
+static int lines_per_block(int n)
+{
+    return std::max(1, std::min(kFftMaxElems / n, 16));
+}
+
+hsd_status fft3d_forward(hipStream_t st, const FftPlan &p, double2 *data)
+{
+    const int n = p.n;
+    const int64_t n2 = (int64_t)n * n;
+    const int bt = lines_per_block(n);
+    const size_t lds = (size_t)bt * n * sizeof(double2);
+    const int ns = (int)p.stages.size();
+    // axis z (contiguous): lines are rows, inner index = row
+    {
+        const int64_t n_inner = n2;
+        dim3 grid((unsigned)((n_inner + bt - 1) / bt), 1);
+        hipLaunchKernelGGL(k_fft_axis, grid, dim3(kFftThreads), lds, st, data, n, bt, (int64_t)1, (int64_t)n,
+                           (int64_t)0, n_inner, p.tw.as<const double2>(), p.plan.as<const int>(), ns);
+        HSD_HIP_TRY(hipGetLastError());
+    }
+    // axis y: element stride n, inner = z (stride 1), outer = x (stride n^2)
+    {
+        dim3 grid((unsigned)((n + bt - 1) / bt), (unsigned)n);
+        hipLaunchKernelGGL(k_fft_axis, grid, dim3(kFftThreads), lds, st, data, n, bt, (int64_t)n, (int64_t)1, n2,
+                           (int64_t)n, p.tw.as<const double2>(), p.plan.as<const int>(), ns);
+        HSD_HIP_TRY(hipGetLastError());
+    }
+    // axis x: element stride n^2, inner = z, outer = y (stride n)
+    {
+        dim3 grid((unsigned)((n + bt - 1) / bt), (unsigned)n);
+        hipLaunchKernelGGL(k_fft_axis, grid, dim3(kFftThreads), lds, st, data, n, bt, n2, (int64_t)1, (int64_t)n,
+                           (int64_t)n, p.tw.as<const double2>(), p.plan.as<const int>(), ns);
+        HSD_HIP_TRY(hipGetLastError());
+    }
+    return HSD_OK;
+}
+
+} // namespace hsd
+
+extern "C" {
+
+// Test hook (not part of the public ABI): forward 3-D FFT of a host cube
+// [n][n][n] of interleaved complex values, in place, on `ctx`'s device.
+int hsd__test_fft3d(hsd_ctx *ctx, double *host_data, int n)
+{
+    using namespace hsd;
+    if (!ctx || !host_data) return HSD_EINVAL;
+    FftPlan plan;
+    hsd_status stt;
+    if ((stt = plan.init(ctx, n)) != HSD_OK) return stt;
+    DevBuf buf;
+    const size_t bytes = (size_t)n * n * n * sizeof(double2);
+    if ((stt = buf.alloc(ctx, bytes)) != HSD_OK) return stt;
+    HSD_HIP_TRY(hipMemcpy(buf.ptr, host_data, bytes, hipMemcpyHostToDevice));
+    if ((stt = fft3d_forward(nullptr, plan, buf.as<double2>())) != HSD_OK) return stt;
+    HSD_HIP_TRY(hipDeviceSynchronize());
+    HSD_HIP_TRY(hipMemcpy(host_data, buf.ptr, bytes, hipMemcpyDeviceToHost));
+    return HSD_OK;
+}
+
+} // extern "C"

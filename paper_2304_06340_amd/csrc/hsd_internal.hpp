@@ -61,6 +61,16 @@ struct Scratch {
     hsd_status ensure(hsd_ctx *c, size_t n);
 };
 
+// Device buffers of the NUFFT path, reused across calls (owned by a context
+// or by a serving slot).
+struct FftPlan;
+struct NufftScratch {
+    DevBuf pts, spts, keys, counts, offs, cursor, perm, grid1, fine, tri, ftq, hinv;
+    std::unique_ptr<FftPlan> plan;
+    NufftScratch();
+    ~NufftScratch();
+};
+
 } // namespace hsd
 
 struct hsd_ctx {
@@ -72,6 +82,8 @@ struct hsd_ctx {
     hsd::Scratch partial;     // [K][N] complex partial transforms
     hsd::Scratch nodebuf;     // per-node residuals / finalize partials
     hsd::Scratch redbuf;      // reduction partials + result
+    hsd::Scratch gradbuf;     // per-triangle and per-vertex gradients
+    hsd::NufftScratch nufft;  // NUFFT grids, points, bins
     double *host_result = nullptr;   // pinned 8-byte readback
     std::mutex mu;
     int num_cu = 256;
@@ -120,6 +132,7 @@ struct hsd_rule {
     hsd::DevBuf d_dirs;                       // SP: [n_dir*3]
     hsd::DevBuf d_wdir;                       // SP: [n_dir]
     hsd::DevBuf d_hx;                         // SP: h*x for the positive half [n/2]
+    hsd::DevBuf d_radii;                      // SP: radial nodes [n_rad]; others: {1.0}
     hsd::DevBuf d_nodes;                      // EXPLICIT/CUBE: [n*3]
     // per-s tables, kept for the rule's lifetime (requests with different s
     // may run concurrently): SP -> radial [n_rad]; general -> per node [n]
@@ -159,15 +172,17 @@ int choose_k_splits_sp(const hsd_rule *rule, int64_t nt, int form, int num_cu, i
 int choose_k_splits_gen(int64_t n, int64_t nt, int num_cu, int req);
 
 // Adjoint (hsd_adjoint.hip).
-hsd_status launch_adjoint(hipStream_t st, const hsd_mesh *m, const hsd_rule *rule,
-                          const double *wtab, const double2 *resid, int form, double tau,
-                          double *tri_grad /*[nt*9]*/);
+int adjoint_splits(int64_t nt, int64_t n_dir, int num_cu);
+hsd_status launch_adjoint_raw(hipStream_t st, const TriRec *tris, int64_t nt, const double *dirs,
+                              int64_t n_dir, const double *radii, int n_rad, const double2 *resid,
+                              const double *wdir, const double *wtab, double tau, int S,
+                              double *part /*[S][nt][10]*/, double *tri_grad /*[nt*9]*/);
 hsd_status launch_gather(hipStream_t st, const hsd_mesh *m, const double *tri_grad,
                          double *grad);
 
 // NUFFT (hsd_nufft.hip).
-hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, const hsd_mesh *mu,
-                                const hsd_mesh *nu, const hsd_rule *rule,
+hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc,
+                                const hsd_mesh *mu, const hsd_mesh *nu, const hsd_rule *rule,
                                 const hsd_params *p, double2 *out, double *pairs);
 
 // Shared host helpers (hsd_core.hip).
@@ -178,7 +193,7 @@ double stated_rel_err(const hsd_params *p, int64_t nt);
 hsd_status distance_core(hsd_ctx *ctx, hipStream_t st, const hsd_mesh *mu, const hsd_mesh *nu,
                          const hsd_rule *rule, const hsd_params *p, bool keep_resid,
                          Scratch &partial, Scratch &nodebuf, Scratch &redbuf,
-                         double **d_result, double *pairs, hipEvent_t ev_tb = nullptr,
-                         hipEvent_t ev_te = nullptr);
+                         NufftScratch &nsc, double **d_result, double *pairs,
+                         hipEvent_t ev_tb = nullptr, hipEvent_t ev_te = nullptr);
 
 } // namespace hsd

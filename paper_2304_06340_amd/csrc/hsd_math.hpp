@@ -106,6 +106,40 @@ HSD_HD cs32 sincos32_from64(double x)
 
 
 
+// FP32 sin/cos of an angle x given in FP64, accurate to ~1 ulp of FP32 in
+// the relative sense also near zero (the hardware unit is not: it carries an
+// absolute error near 1e-7, i.e. ~1e-6 relative for small angles, which the
+// closed-branch differences of the divided difference would amplify).  The
+// angle is reduced by pi/2 in FP64 (Cody-Waite, as sincos64), rounded to
+// FP32 in [-pi/4, pi/4], and the Maclaurin series is summed in FP32
+// (through x^9 for sin, x^10 for cos; remainders below 2e-9).
+HSD_HD cs32 sincos32_acc(double x)
+{
+    const double q = __builtin_rint(x * kTwoOverPi);
+    double rd = __builtin_fma(-q, kPio2Hi, x);
+    rd = __builtin_fma(-q, kPio2Lo, rd);
+    const int iq = (int)q;
+    const float r = (float)rd;
+    const float r2 = r * r;
+    float ps = (float)inv_factorial(9);
+    ps = __builtin_fmaf(ps, r2, (float)-inv_factorial(7));
+    ps = __builtin_fmaf(ps, r2, (float)inv_factorial(5));
+    ps = __builtin_fmaf(ps, r2, (float)-inv_factorial(3));
+    const float sn = __builtin_fmaf(ps * r2, r, r);
+    float pc = (float)-inv_factorial(10);
+    pc = __builtin_fmaf(pc, r2, (float)inv_factorial(8));
+    pc = __builtin_fmaf(pc, r2, (float)-inv_factorial(6));
+    pc = __builtin_fmaf(pc, r2, (float)inv_factorial(4));
+    pc = __builtin_fmaf(pc, r2, -0.5f);
+    const float cn = __builtin_fmaf(pc, r2, 1.0f);
+    const bool swap = (iq & 1) != 0;
+    float s = swap ? cn : sn;
+    float c = swap ? sn : cn;
+    s = (iq & 2) ? -s : s;
+    c = ((iq + 1) & 2) ? -c : c;
+    return cs32{c, s};
+}
+
 // 1/x for finite nonzero x: hardware estimate + two Newton steps (~1 ulp)
 // on the device; a correctly rounded division in the host pass.
 HSD_HD double rcp64(double x)

@@ -1,0 +1,477 @@
+// hsd_nufft.hip -- type-3 NUFFT fast path for mu_h^ on the frequency rule.
+//
+// Every triangle is replaced by the weighted Dirac cloud of a triangle rule
+// {(L(u_q), q_q * area)} (eqs. change_variable, change_variable_approx,
+// Section 3.1), and the exponential sum
+//     f(xi_k) = sum_j c_j exp(-i xi_k . x_j)
+// is evaluated at the nonuniform nodes xi_k by a type-3 NUFFT (the general
+// nonuniform-to-nonuniform case named at the end of Section 3.3), built from
+// the exponential-of-semicircle kernel psi(z) = exp(beta (sqrt(1 - z^2) - 1)):
+//
+//  1. spread: b_l = sum_j c_j Phi(l h1 - x_j) on a grid of spacing
+//     h1 = pi / (sigma S) (S = max |xi_d|), Phi a tensor product of
+//     psi(2 y / (w h1)).  Then sum_j c_j exp(-i xi.x_j) Phi^(xi) =
+//     int b(y) exp(-i xi.y) dy ~= h1^3 sum_l b_l exp(-i (xi h1).l).
+//  2. type 2 on t = xi h1 in [-pi/sigma, pi/sigma]^3: pre-divide b_l by the
+//     Fourier coefficients of the periodised fine-grid kernel, zero-pad to
+//     n2 = sigma n1 (rounded to 2^a 3^b), 3-D FFT, interpolate with the same
+//     kernel shape at t_k.
+//  3. divide by Phi^(xi_k) (Gauss-Legendre quadrature of psi's transform).
+//
+// The spread is a gather (one thread per grid point, points visited in a
+// fixed bin-sorted order), so it is deterministic without atomics on
+// floating-point values; the binning uses integer atomics for counts and
+// placement and then sorts each bin by point index.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "hsd_fft.hpp"
+#include "hsd_internal.hpp"
+#include "hsd_math.hpp"
+
+namespace hsd {
+
+constexpr int kBin = 8;            // grid cells per bin / spread tile edge
+constexpr int kChunk = 64;         // points staged in LDS per spread step
+constexpr int kMaxW = 16;          // largest kernel width supported
+
+struct EsKernel {
+    int w;
+    double beta;
+    double half;                   // w / 2
+};
+
+HSD_HD double es_eval(double z, double beta)
+{
+    const double a = 1.0 - z * z;
+    return a > 0.0 ? exp(beta * (sqrt(a) - 1.0)) : 0.0;
+}
+
+// --------------------------------------------------------------------------
+// 1. points and bins
+// --------------------------------------------------------------------------
+__global__ void k_nufft_points(const TriRec *__restrict__ A, int64_t nA, const TriRec *__restrict__ B, int64_t nB,
+                               const double4 *__restrict__ rule, int nq, double h1, int n1, int nbx,
+                               double4 *__restrict__ pts, int *__restrict__ keys)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t np = (nA + nB) * nq;
+    if (gid >= np) return;
+    const int64_t t = gid / nq;
+    const int q = (int)(gid - t * nq);
+    const bool inA = t < nA;
+    const TriRec T = inA ? A[t] : B[t - nA];
+    const double4 bq = rule[q];   // barycentric (l0, l1, l2) and weight (sum 1)
+    double4 p;
+    p.x = T.p0[0] + bq.y * T.e1[0] + bq.z * T.e2[0];
+    p.y = T.p0[1] + bq.y * T.e1[1] + bq.z * T.e2[1];
+    p.z = T.p0[2] + bq.y * T.e1[2] + bq.z * T.e2[2];
+    p.w = (inA ? 0.5 : -0.5) * T.J * bq.w;
+    pts[gid] = p;
+    const double half = 0.5 * n1;
+    int b[3];
+    const double c[3] = {p.x, p.y, p.z};
+    for (int d = 0; d < 3; ++d) {
+        int v = (int)floor((c[d] / h1 + half) / kBin);
+        b[d] = v < 0 ? 0 : (v >= nbx ? nbx - 1 : v);
+    }
+    keys[gid] = (b[0] * nbx + b[1]) * nbx + b[2];
+}
+
+__global__ void k_bin_count(const int *__restrict__ keys, int64_t np, int *__restrict__ counts)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np) atomicAdd(&counts[keys[i]], 1);
+}
+
+// Exclusive scan of counts[n] into offs[n+1] by one block (fixed order).
+__global__ __launch_bounds__(1024) void k_bin_scan(const int *__restrict__ counts, int n, int *__restrict__ offs)
+{
+    __shared__ int part[1024];
+    const int per = (n + 1023) / 1024;
+    const int b = threadIdx.x * per;
+    int s = 0;
+    for (int i = 0; i < per && b + i < n; ++i) s += counts[b + i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int i = 0; i < 1024; ++i) { const int v = part[i]; part[i] = run; run += v; }
+        offs[n] = run;
+    }
+    __syncthreads();
+    int run = part[threadIdx.x];
+    for (int i = 0; i < per && b + i < n; ++i) { offs[b + i] = run; run += counts[b + i]; }
+}
+
+__global__ void k_bin_place(const int *__restrict__ keys, int64_t np, const int *__restrict__ offs,
+                            int *__restrict__ cursor, int *__restrict__ perm)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const int k = keys[i];
+    perm[offs[k] + atomicAdd(&cursor[k], 1)] = (int)i;
+}
+
+// Canonical order inside each bin: ascending point index (insertion sort).
+__global__ void k_bin_sort(const int *__restrict__ offs, int nbins, int *__restrict__ perm)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nbins) return;
+    const int lo = offs[b], hi = offs[b + 1];
+    for (int i = lo + 1; i < hi; ++i) {
+        const int v = perm[i];
+        int j = i - 1;
+        while (j >= lo && perm[j] > v) { perm[j + 1] = perm[j]; --j; }
+        perm[j + 1] = v;
+    }
+}
+
+__global__ void k_gather_points(const double4 *__restrict__ pts, const int *__restrict__ perm, int64_t np,
+                                double4 *__restrict__ spts)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np) spts[i] = pts[perm[i]];
+}
+
+// --------------------------------------------------------------------------
+// 2. spread (gather form): block = one 8x8x8 tile of grid points
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(512) void k_spread(const double4 *__restrict__ spts, const int *__restrict__ offs,
+                                                int nbx, int n1, double h1, double half_w, double beta,
+                                                double *__restrict__ grid)
+{
+    __shared__ double kv[kChunk][3 * kBin];
+    __shared__ double cw[kChunk];
+    __shared__ double gc[kChunk][3];
+    const int tx = threadIdx.x & 7, ty = (threadIdx.x >> 3) & 7, tz = threadIdx.x >> 6;
+    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    const int org[3] = {bx * kBin, by * kBin, bz * kBin};
+    const double half = 0.5 * n1;
+    const double iw = 1.0 / half_w;
+    double acc = 0.0;
+    for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int nx = bx + dx, ny = by + dy, nz = bz + dz;
+                if (nx < 0 || ny < 0 || nz < 0 || nx >= nbx || ny >= nbx || nz >= nbx) continue;
+                const int nb = (nx * nbx + ny) * nbx + nz;
+                const int lo = offs[nb], hi = offs[nb + 1];
+                for (int c0 = lo; c0 < hi; c0 += kChunk) {
+                    const int cnt = (hi - c0) < kChunk ? (hi - c0) : kChunk;
+                    if ((int)threadIdx.x < cnt) {
+                        const double4 p = spts[c0 + threadIdx.x];
+                        gc[threadIdx.x][0] = p.x / h1 + half;
+                        gc[threadIdx.x][1] = p.y / h1 + half;
+                        gc[threadIdx.x][2] = p.z / h1 + half;
+                        cw[threadIdx.x] = p.w;
+                    }
+                    __syncthreads();
+                    for (int v = threadIdx.x; v < cnt * 3 * kBin; v += 512) {
+                        const int p = v / (3 * kBin), r = v - p * (3 * kBin);
+                        const int d = r / kBin, i = r - d * kBin;
+                        kv[p][r] = es_eval(((double)(org[d] + i) - gc[p][d]) * iw, beta);
+                    }
+                    __syncthreads();
+                    for (int p = 0; p < cnt; ++p)
+                        acc = __builtin_fma(cw[p] * kv[p][tx], kv[p][kBin + ty] * kv[p][2 * kBin + tz], acc);
+                    __syncthreads();
+                }
+            }
+    const int lx = org[0] + tx, ly = org[1] + ty, lz = org[2] + tz;
+    if (lx < n1 && ly < n1 && lz < n1) grid[((int64_t)lx * n1 + ly) * n1 + lz] = acc;
+}
+
+// --------------------------------------------------------------------------
+// 3. pre-deconvolve + zero-pad into the fine grid (index m <-> l' = m or m - n2)
+// --------------------------------------------------------------------------
+__global__ void k_predeconv(const double *__restrict__ grid, int n1, const double *__restrict__ hinv, int n2,
+                            double2 *__restrict__ fine)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t tot = (int64_t)n2 * n2 * n2;
+    if (g >= tot) return;
+    const int mz = (int)(g % n2), my = (int)((g / n2) % n2), mx = (int)(g / ((int64_t)n2 * n2));
+    const int m[3] = {mx, my, mz};
+    int l[3];
+    bool in = true;
+    for (int d = 0; d < 3; ++d) {
+        const int lp = m[d] < n2 / 2 ? m[d] : m[d] - n2;   // signed frequency index
+        l[d] = lp + n1 / 2;
+        in = in && (l[d] >= 0 && l[d] < n1);
+    }
+    double v = 0.0;
+    if (in) v = grid[((int64_t)l[0] * n1 + l[1]) * n1 + l[2]] * hinv[l[0]] * hinv[l[1]] * hinv[l[2]];
+    fine[g] = make_double2(v, 0.0);
+}
+
+// --------------------------------------------------------------------------
+// 4. interpolate at the targets and divide by Phi^
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine, int n2, const double *__restrict__ dirs,
+                                                const double *__restrict__ radii, int n_rad, int64_t N, double h1,
+                                                int w, double beta, const double2 *__restrict__ ftq, int nq,
+                                                double2 *__restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int64_t d = k / n_rad;
+    const int ir = (int)(k - d * n_rad);
+    const double r = radii[ir];
+    const double xi[3] = {r * dirs[3 * d], r * dirs[3 * d + 1], r * dirs[3 * d + 2]};
+    const double half_w = 0.5 * w;
+    const double iw = 1.0 / half_w;
+    const double scale = (double)n2 * h1 / (2.0 * kPi);
+    double wt[3][kMaxW];
+    int base[3];
+    for (int a = 0; a < 3; ++a) {
+        const double u = xi[a] * scale;
+        const int lo = (int)ceil(u - half_w);
+        base[a] = lo;
+        for (int i = 0; i < w; ++i) wt[a][i] = es_eval(((double)(lo + i) - u) * iw, beta);
+    }
+    double re = 0.0, im = 0.0;
+    for (int i = 0; i < w; ++i) {
+        int mx = (base[0] + i) % n2;
+        if (mx < 0) mx += n2;
+        for (int j = 0; j < w; ++j) {
+            int my = (base[1] + j) % n2;
+            if (my < 0) my += n2;
+            const double wxy = wt[0][i] * wt[1][j];
+            const double2 *row = fine + ((int64_t)mx * n2 + my) * n2;
+            double sre = 0.0, sim = 0.0;
+            for (int l = 0; l < w; ++l) {
+                int mz = (base[2] + l) % n2;
+                if (mz < 0) mz += n2;
+                const double2 v = row[mz];
+                sre = __builtin_fma(v.x, wt[2][l], sre);
+                sim = __builtin_fma(v.y, wt[2][l], sim);
+            }
+            re = __builtin_fma(sre, wxy, re);
+            im = __builtin_fma(sim, wxy, im);
+        }
+    }
+    // Phi^(xi) = prod_a (w h1 / 2) 2 sum_q wpsi_q cos(xi_a (w h1 / 2) z_q)
+    double phi = 1.0;
+    const double hw = 0.5 * w * h1;
+    for (int a = 0; a < 3; ++a) {
+        double s = 0.0;
+        for (int q = 0; q < nq; ++q) s += ftq[q].y * sincos64(xi[a] * hw * ftq[q].x).c;
+        phi *= hw * 2.0 * s;
+    }
+    const double n2d = (double)n2;
+    const double f = h1 * h1 * h1 / (n2d * n2d * n2d) / phi;
+    out[k] = make_double2(re * f, im * f);
+}
+
+// --------------------------------------------------------------------------
+// host driver
+// --------------------------------------------------------------------------
+static void tri_rule_table(int kind, std::vector<double4> &tab)
+{
+    tab.clear();
+    if (kind == HSD_TRI_GL8X8) {
+        // 8 x 8 Gauss-Legendre applied twice (iterated integral): u1 = (1+x)/2,
+        // u2 = (1 - u1)(1 + y)/2, weight w_x w_y (1 - u1)/4, times 2 so the
+        // weights sum to 1 (the area ratio of the standard triangle is 1/2)
+        double x[8], wx[8];
+        const double pi = 3.14159265358979323846;
+        for (int i = 0; i < 4; ++i) {
+            double z = std::cos(pi * (i + 0.75) / 8.5);
+            for (int it = 0; it < 100; ++it) {
+                double p0 = 1.0, p1 = z;
+                for (int k = 2; k <= 8; ++k) { double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k; p0 = p1; p1 = pk; }
+                const double dp = 8.0 * (z * p1 - p0) / (z * z - 1.0);
+                const double dz = p1 / dp;
+                z -= dz;
+                if (std::fabs(dz) < 1e-17) break;
+            }
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= 8; ++k) { double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k; p0 = p1; p1 = pk; }
+            const double dp = 8.0 * (z * p1 - p0) / (z * z - 1.0);
+            x[7 - i] = z; x[i] = -z;
+            wx[7 - i] = wx[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+        }
+        for (int i = 0; i < 8; ++i)
+            for (int j = 0; j < 8; ++j) {
+                const double a = 0.5 * (x[i] + 1.0);
+                const double b = (1.0 - a) * 0.5 * (x[j] + 1.0);
+                tab.push_back(make_double4(1.0 - a - b, a, b, wx[i] * wx[j] * (1.0 - a) * 0.5));
+            }
+    } else {
+        // seven-point degree-5 symmetric rule (Radon): centroid and two orbits
+        const double s15 = std::sqrt(15.0);
+        const double al = (6.0 - s15) / 21.0, be = (6.0 + s15) / 21.0;
+        const double wa = (155.0 - s15) / 1200.0, wb = (155.0 + s15) / 1200.0;
+        tab.push_back(make_double4(1.0 / 3.0, 1.0 / 3.0, 1.0 / 3.0, 9.0 / 40.0));
+        const double o[2] = {al, be}, ow[2] = {wa, wb};
+        for (int k = 0; k < 2; ++k) {
+            const double a = o[k], c = 1.0 - 2.0 * o[k];
+            tab.push_back(make_double4(a, a, c, ow[k]));
+            tab.push_back(make_double4(a, c, a, ow[k]));
+            tab.push_back(make_double4(c, a, a, ow[k]));
+        }
+    }
+}
+
+// psi^ quadrature nodes on [0, 1]: (z_q, w_q psi(z_q)).
+static void es_ft_table(double beta, int q, std::vector<double2> &tab)
+{
+    std::vector<double> x(q), wx(q);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < (q + 1) / 2; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (q + 0.5)), p0, p1, dp;
+        for (int it = 0; it < 100; ++it) {
+            p0 = 1.0; p1 = z;
+            for (int k = 2; k <= q; ++k) { double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k; p0 = p1; p1 = pk; }
+            dp = q * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        p0 = 1.0; p1 = z;
+        for (int k = 2; k <= q; ++k) { double pk = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k; p0 = p1; p1 = pk; }
+        dp = q * (z * p1 - p0) / (z * z - 1.0);
+        x[q - 1 - i] = z; x[i] = -z;
+        wx[q - 1 - i] = wx[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+    tab.resize(q);
+    for (int i = 0; i < q; ++i) {
+        const double z = 0.5 * (x[i] + 1.0);
+        tab[i] = make_double2(z, 0.5 * wx[i] * es_eval(z, beta));
+    }
+}
+
+static double es_ft_host(const std::vector<double2> &tab, double k)
+{
+    double s = 0.0;
+    for (const auto &t : tab) s += t.y * std::cos(k * t.x);
+    return 2.0 * s;
+}
+
+NufftScratch::NufftScratch() = default;
+NufftScratch::~NufftScratch() = default;
+
+hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, const hsd_mesh *mu,
+                                const hsd_mesh *nu, const hsd_rule *rule, const hsd_params *p, double2 *out,
+                                double *pairs)
+{
+    hsd_status stt;
+    const double sigma = p->nufft_sigma > 1.0 ? p->nufft_sigma : 2.0;
+    int w = p->nufft_width;
+    if (w <= 0) w = (int)std::ceil(std::log10(1.0 / std::max(p->nufft_tol, 1e-16))) + 1;
+    w = std::max(2, std::min(w, kMaxW));
+    const double beta = 0.97 * kPi * (1.0 - 0.5 / sigma) * w;
+    // extent of the sources and of the targets per dimension
+    double X = 0.0;
+    for (const hsd_mesh *m : {mu, nu}) {
+        if (!m) continue;
+        for (double v : m->host_verts) X = std::max(X, std::fabs(v));
+    }
+    X = std::max(X, 1e-3);
+    double S = 0.0;
+    const bool sp = rule->kind == HSD_RULE_SPHERICAL_PRODUCT;
+    if (sp) {
+        S = rule->sp.r_max;
+    } else {
+        for (double v : rule->host_nodes) S = std::max(S, std::fabs(v));
+    }
+    S = std::max(S, 1e-3);
+    const double h1 = kPi / (sigma * S);
+    int n1 = (int)std::ceil(2.0 * X / h1 + w + 2);
+    n1 += n1 & 1;
+    const int n2 = fft_next_size((int)std::ceil(sigma * n1));
+    if (!fft_size_ok(n2) || n2 > 2048) {
+        set_error("NUFFT grid %d^3 exceeds the supported FFT size (2048)", n2);
+        return HSD_EINVAL;
+    }
+    const int nbx = (n1 + kBin - 1) / kBin;
+    const int nbins = nbx * nbx * nbx;
+    std::vector<double4> trule;
+    tri_rule_table(p->tri_rule, trule);
+    const int nq = (int)trule.size();
+    const int64_t ntri = mu->nt + (nu ? nu->nt : 0);
+    const int64_t np = ntri * nq;
+    // kernel-transform tables
+    std::vector<double2> ftq;
+    es_ft_table(beta, 4 * w + 24, ftq);
+    std::vector<double> hinv(n1);
+    for (int l = 0; l < n1; ++l) {
+        const int lp = l - n1 / 2;
+        // H^_l = (1/2pi) int h(t) e^{-ilt} dt with h(t) = psi(t n2 / (pi w))
+        const double Hl = (double)w / (2.0 * n2) * es_ft_host(ftq, lp * w * kPi / n2);
+        hinv[l] = 1.0 / Hl;
+    }
+    const int64_t N = rule->n_nodes;
+    if ((stt = sc.tri.alloc(ctx, trule.size() * sizeof(double4))) != HSD_OK) return stt;
+    if ((stt = sc.ftq.alloc(ctx, ftq.size() * sizeof(double2))) != HSD_OK) return stt;
+    if ((stt = sc.hinv.alloc(ctx, hinv.size() * sizeof(double))) != HSD_OK) return stt;
+    HSD_HIP_TRY(hipMemcpyAsync(sc.tri.ptr, trule.data(), trule.size() * sizeof(double4), hipMemcpyHostToDevice, st));
+    HSD_HIP_TRY(hipMemcpyAsync(sc.ftq.ptr, ftq.data(), ftq.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+    HSD_HIP_TRY(hipMemcpyAsync(sc.hinv.ptr, hinv.data(), hinv.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    auto ens = [&](DevBuf &b, size_t bytes) -> hsd_status {
+        if (b.ptr && b.bytes >= bytes) return HSD_OK;
+        return b.alloc(ctx, std::max<size_t>(bytes, 8));
+    };
+    if ((stt = ens(sc.pts, (size_t)np * sizeof(double4))) != HSD_OK) return stt;
+    if ((stt = ens(sc.spts, (size_t)np * sizeof(double4))) != HSD_OK) return stt;
+    if ((stt = ens(sc.keys, (size_t)np * sizeof(int))) != HSD_OK) return stt;
+    if ((stt = ens(sc.perm, (size_t)np * sizeof(int))) != HSD_OK) return stt;
+    if ((stt = ens(sc.counts, (size_t)nbins * sizeof(int))) != HSD_OK) return stt;
+    if ((stt = ens(sc.cursor, (size_t)nbins * sizeof(int))) != HSD_OK) return stt;
+    if ((stt = ens(sc.offs, ((size_t)nbins + 1) * sizeof(int))) != HSD_OK) return stt;
+    if ((stt = ens(sc.grid1, (size_t)n1 * n1 * n1 * sizeof(double))) != HSD_OK) return stt;
+    if ((stt = ens(sc.fine, (size_t)n2 * n2 * n2 * sizeof(double2))) != HSD_OK) return stt;
+    if (!sc.plan || sc.plan->n != n2) {
+        sc.plan.reset(new FftPlan());
+        if ((stt = sc.plan->init(ctx, n2)) != HSD_OK) return stt;
+    }
+    const FftPlan &plan = *sc.plan;
+
+    const TriRec *A = mu->tris.as<const TriRec>();
+    const TriRec *B = nu ? nu->tris.as<const TriRec>() : nullptr;
+    const int64_t nB = nu ? nu->nt : 0;
+    HSD_HIP_TRY(hipMemsetAsync(sc.counts.ptr, 0, (size_t)nbins * sizeof(int), st));
+    HSD_HIP_TRY(hipMemsetAsync(sc.cursor.ptr, 0, (size_t)nbins * sizeof(int), st));
+    if (np > 0) {
+        const unsigned g = (unsigned)((np + 255) / 256);
+        hipLaunchKernelGGL(k_nufft_points, dim3(g), dim3(256), 0, st, A, mu->nt, B, nB, sc.tri.as<const double4>(), nq,
+                           h1, n1, nbx, sc.pts.as<double4>(), sc.keys.as<int>());
+        HSD_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(256), 0, st, sc.keys.as<const int>(), np, sc.counts.as<int>());
+        HSD_HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, sc.counts.as<const int>(), nbins, sc.offs.as<int>());
+    HSD_HIP_TRY(hipGetLastError());
+    if (np > 0) {
+        const unsigned g = (unsigned)((np + 255) / 256);
+        hipLaunchKernelGGL(k_bin_place, dim3(g), dim3(256), 0, st, sc.keys.as<const int>(), np, sc.offs.as<const int>(),
+                           sc.cursor.as<int>(), sc.perm.as<int>());
+        HSD_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_bin_sort, dim3((nbins + 255) / 256), dim3(256), 0, st, sc.offs.as<const int>(), nbins,
+                           sc.perm.as<int>());
+        HSD_HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(k_gather_points, dim3(g), dim3(256), 0, st, sc.pts.as<const double4>(),
+                           sc.perm.as<const int>(), np, sc.spts.as<double4>());
+        HSD_HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_spread, dim3(nbx, nbx, nbx), dim3(512), 0, st, sc.spts.as<const double4>(),
+                       sc.offs.as<const int>(), nbx, n1, h1, 0.5 * w, beta, sc.grid1.as<double>());
+    HSD_HIP_TRY(hipGetLastError());
+    const int64_t tot2 = (int64_t)n2 * n2 * n2;
+    hipLaunchKernelGGL(k_predeconv, dim3((unsigned)((tot2 + 255) / 256)), dim3(256), 0, st, sc.grid1.as<const double>(),
+                       n1, sc.hinv.as<const double>(), n2, sc.fine.as<double2>());
+    HSD_HIP_TRY(hipGetLastError());
+    if ((stt = fft3d_forward(st, plan, sc.fine.as<double2>())) != HSD_OK) return stt;
+    const double *dirs = sp ? rule->d_dirs.as<const double>() : rule->d_nodes.as<const double>();
+    const int n_rad = sp ? (int)rule->n_rad : 1;
+    hipLaunchKernelGGL(k_interp, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, sc.fine.as<const double2>(), n2,
+                       dirs, rule->d_radii.as<const double>(), n_rad, N, h1, w, beta, sc.ftq.as<const double2>(),
+                       (int)ftq.size(), out);
+    HSD_HIP_TRY(hipGetLastError());
+    if (pairs) *pairs = (double)np;
+    return HSD_OK;
+}
+
+} // namespace hsd

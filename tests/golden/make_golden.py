@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
-from hsd_inputs import icosphere  # noqa: E402
+from hsd_inputs import icosphere, perturb_harmonic  # noqa: E402
 
 # the configurations (rule parameters) the fixtures refer to
 RULE_SMALL = dict(r_max=64.0, n_panels=8, n_per_panel=16, n_cos=32, n_phi=64)      # 262,144 nodes
@@ -67,7 +67,22 @@ def d2_levels(name, levels, spec, s=1.0):
         json.dump(out, open(path, "w"), indent=1)
 
 
+def adjoint_case(name, level=4, spec=RULE_SMALL, amp=0.05, s=1.0):
+    """d^2 and its vertex gradient for the radially perturbed icosphere
+    v <- v_hat (1 + amp sin(3 theta) cos(2 phi)) against S^2."""
+    v, f = icosphere(level)
+    v = perturb_harmonic(v, amp)
+    rule = _rule(spec)
+    t = time.time()
+    d2, g = oracle.gradient(v, f, rule, s=s)
+    dt = time.time() - t
+    np.savez(os.path.join(HERE, name + ".npz"), d2=d2, grad=g, level=level, amp=amp, s=s,
+             rule=json.dumps(spec), note="oracle.gradient (dual numbers); written by make_golden.py")
+    print(f"{name}: d2={d2!r} |grad|max={np.abs(g).max():.3e} ({dt:.1f}s)", flush=True)
+
+
 JOBS = {
+    "adjoint_level4_small_rule": lambda: adjoint_case("adjoint_level4_small_rule"),
     "small_rule_levels": lambda: d2_levels("small_rule_levels", range(0, 6), RULE_SMALL),
     "level7_small_rule_sampled": lambda: sampled("level7_small_rule_sampled", 7, RULE_SMALL),
     "level7_large_rule_sampled": lambda: sampled("level7_large_rule_sampled", 7, RULE_LARGE),

@@ -1,0 +1,102 @@
+"""GPU checks of the type-3 NUFFT path: its FFT against numpy, and its
+transform against the oracle's direct sum over exactly the same point cloud
+(the NUFFT error), plus the point-rule model error against the exact
+triangle transform (reported, unpinned)."""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+import paper_2304_06340_amd as hsd
+from hsd_inputs import icosphere, perturb_radial, random_rotation, rotate
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n", [8, 12, 24, 27, 48, 64, 96, 192])
+def test_fft3d_against_numpy(hsd_ctx, n):
+    L = hsd_ctx._lib
+    f = L.hsd__test_fft3d
+    f.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int]
+    rng = np.random.default_rng(n)
+    x = rng.normal(size=(n, n, n)) + 1j * rng.normal(size=(n, n, n))
+    buf = np.ascontiguousarray(np.stack([x.real, x.imag], axis=-1))
+    assert f(hsd_ctx.handle, buf.ctypes.data_as(C.POINTER(C.c_double)), n) == 0
+    got = buf[..., 0] + 1j * buf[..., 1]
+    ref = np.fft.fftn(x)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    assert err <= 5e-15 * math.log2(n ** 3), err
+
+
+SPEC = dict(r_max=24.0, n_panels=3, n_per_panel=8, n_cos=12, n_phi=24)
+
+
+@pytest.mark.parametrize("tri_rule", ["dunavant7", "gl8x8"])
+@pytest.mark.parametrize("width,tol", [(8, 1e-7), (0, 1e-9)])
+def test_nufft_against_direct_point_sum(hsd_ctx, orc, tri_rule, width, tol):
+    rng = np.random.default_rng(3)
+    v, f = icosphere(2)
+    v = rotate(perturb_radial(v, 0.01, rng), random_rotation(rng))
+    rule = hsd.Rule.spherical_product(hsd_ctx, **SPEC)
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    p = hsd.Params(method="nufft3", tri_rule=tri_rule, nufft_width=width, nufft_tol=1e-9)
+    got = hsd.transform_rule(hsd_ctx, mesh, rule, p)
+    o = orc.spherical_product_rule(**SPEC)
+    pts, c = orc.point_cloud(v, f, tri_rule)
+    ref = orc.point_sum(pts, c, o.nodes)
+    err = np.max(np.abs(got - ref)) / np.sum(np.abs(c))
+    print(f"{tri_rule} w={width or 'tol'}: max |err| / sum|c| = {err:.2e}")
+    assert err <= tol
+
+
+def test_nufft_explicit_nodes_and_mesh_vs_mesh(hsd_ctx, orc):
+    rng = np.random.default_rng(6)
+    v, f = icosphere(2)
+    v2, f2 = icosphere(1)
+    v2 = rotate(v2, random_rotation(rng)) * 1.03
+    x = rng.normal(size=(3000, 3)) * 6
+    w = rng.uniform(0.1, 1.0, 3000)
+    rule = hsd.Rule.explicit(hsd_ctx, x, w)
+    m1, m2 = hsd.Mesh(hsd_ctx, v, f), hsd.Mesh(hsd_ctx, v2, f2)
+    p = hsd.Params(method="nufft3", nufft_tol=1e-9)
+    got = hsd.transform_rule(hsd_ctx, m1, rule, p)
+    pts, c = orc.point_cloud(v, f)
+    ref = orc.point_sum(pts, c, x)
+    assert np.max(np.abs(got - ref)) <= 1e-9 * np.sum(np.abs(c))
+    # mesh vs mesh distance through the NUFFT against the direct point sums
+    res = hsd.distance(hsd_ctx, m1, m2, rule, p)
+    pts2, c2 = orc.point_cloud(v2, f2)
+    R = ref - orc.point_sum(pts2, c2, x)
+    W = orc.sobolev_weights(orc.Rule(x, w), 1.0)
+    d2_ref = math.fsum(W * np.abs(R) ** 2)
+    assert abs(res.d2 - d2_ref) <= 1e-7 * d2_ref
+
+
+def test_nufft_distance_model_error_and_determinism(hsd_ctx, orc):
+    """d^2 from the NUFFT path vs (i) the same d^2 from the direct point sum
+    (NUFFT error, pinned) and (ii) the exact-triangle d^2 (the point-rule
+    model error of Section 3.1, reported only)."""
+    for spec, levels in ((SPEC, (2,)), (dict(r_max=64.0, n_panels=8, n_per_panel=16, n_cos=32, n_phi=64),
+                                         (2, 3, 4))):
+        rule = hsd.Rule.spherical_product(hsd_ctx, **spec)
+        o = orc.spherical_product_rule(**spec)
+        W = orc.sobolev_weights(o, 1.0)
+        nu = orc.nu_hat_sphere(o.radii)
+        for level in levels:
+            v, f = icosphere(level)
+            mesh = hsd.Mesh(hsd_ctx, v, f)
+            exact = hsd.distance(hsd_ctx, mesh, None, rule).d2
+            for tri_rule in ("dunavant7", "gl8x8"):
+                p = hsd.Params(method="nufft3", tri_rule=tri_rule, nufft_tol=1e-9)
+                r1 = hsd.distance(hsd_ctx, mesh, None, rule, p)
+                r2 = hsd.distance(hsd_ctx, mesh, None, rule, p)
+                assert r1.d2 == r2.d2
+                print(f"rule {len(o)} nodes, level {level} {tri_rule}: nufft d2 {r1.d2:.10e}, "
+                      f"exact {exact:.10e}, model rel err {abs(r1.d2 - exact) / exact:.2e}, "
+                      f"{r1.device_ms:.2f} ms")
+                if spec is SPEC:
+                    pts, c = orc.point_cloud(v, f, tri_rule)
+                    mu = orc.point_sum(pts, c, o.nodes)
+                    d2_pts = math.fsum(W * np.abs(mu - nu) ** 2)
+                    assert abs(r1.d2 - d2_pts) <= 1e-6 * d2_pts, (r1.d2, d2_pts)
