@@ -74,6 +74,10 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-nodes", type=int, default=2048)
+    ap.add_argument("--no-nufft", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=512)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -141,6 +145,44 @@ def main():
                         "rel_err_stated": resm[-1].rel_err_stated,
                         "speedup_vs_fp64": wall64 / wallm,
                         "kernel_ms": float(np.mean([r.transform_ms for r in resm]))}
+    if not args.no_nufft:
+        # type-3 NUFFT fast path (Dunavant-7 points, tol 1e-9) on the same mesh and rule
+        pn = hsd.Params(s=1.0, method="nufft3", nufft_tol=1e-9)
+        walln, resn = run(pn, max(1, args.steps), 1)
+        out["nufft"] = {"ms_per_step": walln * 1e3, "distances_per_s": 1.0 / walln,
+                        "points": resn[-1].pairs, "rel_err_vs_fp64_direct": abs(resn[-1].d2 - d2_64) / d2_64,
+                        "note": "error vs the exact-triangle d2 includes the 7-point rule's model error"}
+    if not args.no_adjoint:
+        from hsd_inputs import perturb_harmonic
+        va, fa = icosphere(4)
+        va = perturb_harmonic(va, 0.05)
+        ma = hsd.Mesh(ctx, va, fa)
+        ra = hsd.Rule.spherical_product(ctx, r_max=64.0, n_panels=8, n_per_panel=16, n_cos=32, n_phi=64)
+        hsd.distance_grad(ctx, ma, None, ra)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            ga = hsd.distance_grad(ctx, ma, None, ra)[0]
+        torch.cuda.synchronize()
+        wa = (time.perf_counter() - t0) / 3
+        out["adjoint"] = {"workload": "level-4 icosphere, v(1+0.05 sin3t cos2p), 262,144-node rule",
+                          "ms_per_gradient": wa * 1e3, "pairs": ga.pairs}
+        ma.close()
+        ra.close()
+    if not args.no_serve:
+        from hsd_inputs import serving_trace
+        from paper_2304_06340_amd.serving import replay
+        trace = serving_trace(n=args.serve_requests, rate=20.0, seed=0, p_large=0.01)
+        rules = {"small": hsd.Rule.spherical_product(ctx, r_max=64.0, n_panels=8, n_per_panel=16,
+                                                     n_cos=32, n_phi=64),
+                 "large": rule}
+        out["serving"] = {"trace": f"{len(trace)} requests, Poisson 20/s, seed 0, levels 1-6, 30% "
+                                   "mesh-vs-mesh, 1% on the large rule", "slots": 4}
+        for form in ("fp64", "mixed"):
+            with hsd.Server(ctx, slots=4, chunk_pairs=20_000_000_000) as srv:
+                st = replay(srv, trace, rules, hsd.Params(s=1.0, form=form))
+            st.pop("results")
+            out["serving"][form] = st
     if not args.no_cpu:
         import oracle
         orule = oracle.spherical_product_rule(**spec)

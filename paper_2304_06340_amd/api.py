@@ -268,3 +268,101 @@ def transform_rule(ctx: Context, mesh: Mesh, rule: Rule, params: Params | None =
     _check(ctx._lib.hsd_transform_rule(ctx.handle, mesh.handle, rule.handle, C.byref(p),
                                        out.ctypes.data_as(C.c_void_p), L.MEM_HOST))
     return out[0::2] + 1j * out[1::2]
+
+
+@dataclass
+class Ticket:
+    status: int
+    result: Result
+    arrival_s: float
+    admitted_s: float
+    finished_s: float
+    footprint: int
+    error: str = ""
+
+    @property
+    def latency_s(self) -> float:
+        return self.finished_s - self.arrival_s
+
+
+class Server:
+    """Continuous-batching request loop (hsd_server_*).  Requests are copied
+    at submit; results are fetched with poll() / wait()."""
+
+    def __init__(self, ctx: Context | None, slots: int = 4, queue_capacity: int = 4096,
+                 budget_bytes: int = 64 << 30, chunk_pairs: int = 20_000_000_000, _fake_rate: float | None = None):
+        self.ctx = ctx
+        self._lib = L.load()
+        cfg = L.ServerCfg()
+        cfg.slots, cfg.queue_capacity = int(slots), int(queue_capacity)
+        cfg.hbm_budget_bytes, cfg.chunk_pairs = int(budget_bytes), int(chunk_pairs)
+        h = C.c_void_p()
+        if _fake_rate is None:
+            _check(self._lib.hsd_server_create(ctx.handle, C.byref(cfg), C.byref(h)))
+        else:
+            f = self._lib.hsd__server_create_fake
+            f.restype = C.c_int32
+            f.argtypes = [C.POINTER(L.ServerCfg), C.c_double, C.POINTER(C.c_void_p)]
+            _check(f(C.byref(cfg), float(_fake_rate), C.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    @classmethod
+    def fake(cls, slots=2, queue_capacity=64, budget_bytes=1 << 30, chunk_pairs=1_000_000,
+             pairs_per_s=1e8) -> "Server":
+        """A server whose executor simulates the work on the CPU (tests)."""
+        return cls(None, slots, queue_capacity, budget_bytes, chunk_pairs, _fake_rate=pairs_per_s)
+
+    def submit(self, verts, tris, rule: Rule | None = None, params: Params | None = None,
+               verts2=None, tris2=None, tag: int = 0) -> int:
+        v = _host_f64(verts, 3)
+        t = _host_i32(tris)
+        req = L.Request()
+        req.verts, req.nv = v.ctypes.data_as(L.dp), len(v)
+        req.tris, req.nt = t.ctypes.data_as(L.ip), len(t)
+        if verts2 is not None:
+            v2 = _host_f64(verts2, 3)
+            t2 = _host_i32(tris2)
+            req.verts2, req.nv2 = v2.ctypes.data_as(L.dp), len(v2)
+            req.tris2, req.nt2 = t2.ctypes.data_as(L.ip), len(t2)
+        req.rule = rule.handle if rule is not None else None
+        req.params = (params or Params()).to_c()
+        req.tag = int(tag)
+        tk = C.c_uint64()
+        _check(self._lib.hsd_submit(self.handle, C.byref(req), C.byref(tk)))
+        return int(tk.value)
+
+    def _ticket(self, st, r, tm) -> Ticket:
+        err = self._lib.hsd_last_error().decode(errors="replace") if st < 0 else ""
+        return Ticket(int(st), Result.from_c(r), tm.arrival_s, tm.admitted_s, tm.finished_s, tm.footprint, err)
+
+    def poll(self, ticket: int) -> Ticket:
+        r, tm = L.Result(), L.RequestTimes()
+        st = self._lib.hsd_poll(self.handle, C.c_uint64(ticket), C.byref(r), C.byref(tm))
+        if st == L.HSD_ENOTFOUND:
+            _check(st)
+        return self._ticket(st, r, tm)
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> Ticket:
+        r, tm = L.Result(), L.RequestTimes()
+        st = self._lib.hsd_wait(self.handle, C.c_uint64(ticket), float(timeout_s), C.byref(r), C.byref(tm))
+        if st == L.HSD_ENOTFOUND:
+            _check(st)
+        return self._ticket(st, r, tm)
+
+    def cancel(self, ticket: int) -> None:
+        _check(self._lib.hsd_cancel(self.handle, C.c_uint64(ticket)))
+
+    def release(self, ticket: int) -> None:
+        _check(self._lib.hsd_release(self.handle, C.c_uint64(ticket)))
+
+    def close(self) -> None:
+        if self.handle:
+            self._lib.hsd_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -41,8 +41,9 @@ namespace hsd {
 constexpr int kTile = 32;          // triangles per blocked-summation tile
 constexpr double kGapFloor = 1e-150;
 // The mixed form evaluates the closed branch in FP32, whose cancellation
-// error is about eps32 / G; it switches to the FP64 series below
-// max(tau, kMixedTau) (the series is still exact to 1e-20 there).
+// error is about eps32 / G relative to J; below G = kMixedTau it sums the
+// series in FP32 instead (no cancellation: absolute error ~eps32; terms
+// beyond n = 9 are below 3e-11 at G = 0.5).
 constexpr double kMixedTau = 0.05;
 // Gap floor of the mixed form: keeps 2J/(gap G) finite in FP32 (an exactly
 // zero gap becomes 1e-18, changing mu_T by ~1e-18 relative).
@@ -185,6 +186,7 @@ HSD_HD void sp_lane_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t 
             const float Ka = (float)(2.0 * J * rcp64(ac) * iG);
             const float Kb = (float)(2.0 * J * rcp64(bc) * iG);
             const double r_thr = fmax(tau, kMixedTau) * iG;
+            const float acf = (float)ac, bcf = (float)bc;
             const double fr[3] = {tmid, 0.5 * ac, 0.5 * bc};
             cs32 Bk[3], S[3], Cp[3];
 #pragma unroll
@@ -209,18 +211,23 @@ HSD_HD void sp_lane_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t 
                         Eu = sg == 0 ? pmul(Cp[1], Bk[1]) : pmulc(Cp[1], Bk[1]);
                         Ev = sg == 0 ? pmul(Cp[2], Bk[2]) : pmulc(Cp[2], Bk[2]);
                     }
-                    const float Pv = Kb * Ev.s;
-                    const float Pu = Ka * Eu.s;
-                    float Yr = __builtin_fmaf(Pv, Ev.s, Pu * Eu.s);
-                    float Xr = __builtin_fmaf(Pv, Ev.c, -Pu * Eu.c);
-                    if ((double)rr[slot] < r_thr) {
+                    float Yr, Xr;
+                    const float r = rr[slot];
+                    if ((double)r < r_thr) {
+                        float fre, fim;
+                        dd2_series(r * acf, r * bcf, fre, fim);
+                        // r^2 J formed in FP64 and rounded once: an FP32 r^2
+                        // would bias every term of the node the same way
                         const double m = (double)(2 * (p0 + pl) + 1) * h;
                         const double rd = sg == 0 ? m + hx : m - hx;
-                        double fre, fim;
-                        dd2_series(rd * ac, rd * bc, fre, fim);
-                        const double r2J = rd * rd * J;
-                        Yr = (float)(r2J * fre);
-                        Xr = (float)(r2J * fim);
+                        const float r2J = (float)(rd * rd * J);
+                        Yr = r2J * fre;
+                        Xr = r2J * fim;
+                    } else {
+                        const float Pv = Kb * Ev.s;
+                        const float Pu = Ka * Eu.s;
+                        Yr = __builtin_fmaf(Pv, Ev.s, Pu * Eu.s);
+                        Xr = __builtin_fmaf(Pv, Ev.c, -Pu * Eu.c);
                     }
                     acc_re[slot] += __builtin_fmaf(E1.c, Yr, E1.s * Xr);
                     acc_im[slot] += __builtin_fmaf(E1.c, Xr, -E1.s * Yr);
@@ -300,10 +307,10 @@ HSD_HD void gen_node_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t
             const cs32 E1 = sincos32_acc(t0 + mid);
             float Yr, Xr;
             if (a + b < fmax(tau, kMixedTau)) {
-                double fre, fim;
-                dd2_series(a, b, fre, fim);
-                Yr = (float)(J * fre);
-                Xr = (float)(J * fim);
+                float fre, fim;
+                dd2_series((float)a, (float)b, fre, fim);
+                Yr = (float)J * fre;
+                Xr = (float)J * fim;
             } else {
                 const double ac = fmax(a, kGapFloor32), bc = fmax(b, kGapFloor32);
                 const double iG = rcp64(ac + bc);
@@ -335,18 +342,18 @@ HSD_HD void gen_node_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t
 template <int PG, int FORM>
 __global__ __launch_bounds__(256) void k_direct_sp(
     const TriRec *__restrict__ A, int64_t nA, const TriRec *__restrict__ B, int64_t nB,
-    const double *__restrict__ dirs, const double *__restrict__ hx_tab, int n_dir, int n_half,
-    int n, int P, double h, double tau, int64_t N, double2 *__restrict__ partial)
+    const double *__restrict__ dirs, const double *__restrict__ hx_tab, int64_t d_begin, int64_t d_count,
+    int n_half, int n, int P, double h, double tau, int64_t N, double2 *__restrict__ partial)
 {
     constexpr int NS = 2 * PG;
     const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t n_lanes = (int64_t)(P / PG) * n_dir * n_half;
+    const int64_t n_lanes = (int64_t)(P / PG) * d_count * n_half;
     const bool active = lane < n_lanes;
     const int64_t L = active ? lane : 0;
     const int k = (int)(L % n_half);
     const int64_t gd = L / n_half;
-    const int d = (int)(gd % n_dir);
-    const int g = (int)(gd / n_dir);
+    const int64_t d = d_begin + gd % d_count;
+    const int g = (int)(gd / d_count);
     const int p0 = g * PG;
     const int64_t ntot = nA + nB;
     const int K = gridDim.y;
@@ -379,10 +386,11 @@ __global__ __launch_bounds__(256) void k_direct_sp(
 template <int FORM>
 __global__ __launch_bounds__(256) void k_direct_gen(
     const TriRec *__restrict__ A, int64_t nA, const TriRec *__restrict__ B, int64_t nB,
-    const double *__restrict__ nodes, int64_t n, double tau, double2 *__restrict__ partial)
+    const double *__restrict__ nodes, int64_t n, int64_t i_begin, int64_t i_count, double tau,
+    double2 *__restrict__ partial)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = i < n;
+    const int64_t i = i_begin + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < i_begin + i_count;
     const int64_t I = active ? i : 0;
     const int64_t ntot = nA + nB;
     const int K = gridDim.y;
@@ -545,13 +553,14 @@ int choose_k_splits_gen(int64_t n, int64_t nt, int num_cu, int req)
 }
 
 template <int PG>
-static hsd_status launch_sp_pg(hipStream_t st, const MeshPair &mp, const hsd_rule *rule, int form,
-                               double tau, int K, double2 *partial)
+static hsd_status launch_sp_pg(hipStream_t st, const MeshPair &mp, const hsd_rule *rule, int form, double tau,
+                               int K, int64_t d_begin, int64_t d_count, double2 *partial)
 {
     const RuleSP &sp = rule->sp;
     const int n_half = sp.n / 2;
-    const int64_t lanes = (int64_t)(sp.P / PG) * rule->n_dir * n_half;
+    const int64_t lanes = (int64_t)(sp.P / PG) * d_count * n_half;
     const int64_t blocks = (lanes + 255) / 256;
+    if (lanes <= 0) return HSD_OK;
     if (blocks > INT32_MAX || K > 65535) {
         set_error("direct_sp: grid too large (%lld blocks, K=%d)", (long long)blocks, K);
         return HSD_EINVAL;
@@ -559,32 +568,39 @@ static hsd_status launch_sp_pg(hipStream_t st, const MeshPair &mp, const hsd_rul
     dim3 grid((unsigned)blocks, (unsigned)K), block(256);
     if (form == HSD_FORM_FP64)
         hipLaunchKernelGGL((k_direct_sp<PG, HSD_FORM_FP64>), grid, block, 0, st, mp.A, mp.nA, mp.B, mp.nB,
-                           rule->d_dirs.as<const double>(), rule->d_hx.as<const double>(),
-                           (int)rule->n_dir, n_half, sp.n, sp.P, sp.h, tau, rule->n_nodes, partial);
+                           rule->d_dirs.as<const double>(), rule->d_hx.as<const double>(), d_begin, d_count,
+                           n_half, sp.n, sp.P, sp.h, tau, rule->n_nodes, partial);
     else
         hipLaunchKernelGGL((k_direct_sp<PG, HSD_FORM_MIXED>), grid, block, 0, st, mp.A, mp.nA, mp.B, mp.nB,
-                           rule->d_dirs.as<const double>(), rule->d_hx.as<const double>(),
-                           (int)rule->n_dir, n_half, sp.n, sp.P, sp.h, tau, rule->n_nodes, partial);
+                           rule->d_dirs.as<const double>(), rule->d_hx.as<const double>(), d_begin, d_count,
+                           n_half, sp.n, sp.P, sp.h, tau, rule->n_nodes, partial);
     HSD_HIP_TRY(hipGetLastError());
     return HSD_OK;
 }
 
-hsd_status launch_direct_sp(hipStream_t st, const MeshPair &mp, const hsd_rule *rule, int form,
-                            double tau, int K, double2 *partial)
+hsd_status launch_direct_sp_range(hipStream_t st, const MeshPair &mp, const hsd_rule *rule, int form,
+                                  double tau, int K, int64_t d_begin, int64_t d_count, double2 *partial)
 {
     switch (pick_pg(rule->sp.P, form)) {
-    case 8: return launch_sp_pg<8>(st, mp, rule, form, tau, K, partial);
-    case 4: return launch_sp_pg<4>(st, mp, rule, form, tau, K, partial);
-    case 2: return launch_sp_pg<2>(st, mp, rule, form, tau, K, partial);
-    default: return launch_sp_pg<1>(st, mp, rule, form, tau, K, partial);
+    case 8: return launch_sp_pg<8>(st, mp, rule, form, tau, K, d_begin, d_count, partial);
+    case 4: return launch_sp_pg<4>(st, mp, rule, form, tau, K, d_begin, d_count, partial);
+    case 2: return launch_sp_pg<2>(st, mp, rule, form, tau, K, d_begin, d_count, partial);
+    default: return launch_sp_pg<1>(st, mp, rule, form, tau, K, d_begin, d_count, partial);
     }
 }
 
-hsd_status launch_direct_gen(hipStream_t st, const MeshPair &mp, const double *nodes, int64_t n,
-                             int form, double tau, int K, double2 *partial)
+hsd_status launch_direct_sp(hipStream_t st, const MeshPair &mp, const hsd_rule *rule, int form, double tau,
+                            int K, double2 *partial)
 {
-    const int64_t blocks = (n + 255) / 256;
-    if (n <= 0) return HSD_OK;
+    return launch_direct_sp_range(st, mp, rule, form, tau, K, 0, rule->n_dir, partial);
+}
+
+hsd_status launch_direct_gen_range(hipStream_t st, const MeshPair &mp, const double *nodes, int64_t n,
+                                   int form, double tau, int K, int64_t i_begin, int64_t i_count,
+                                   double2 *partial)
+{
+    const int64_t blocks = (i_count + 255) / 256;
+    if (i_count <= 0) return HSD_OK;
     if (blocks > INT32_MAX || K > 65535) {
         set_error("direct_gen: grid too large");
         return HSD_EINVAL;
@@ -592,12 +608,18 @@ hsd_status launch_direct_gen(hipStream_t st, const MeshPair &mp, const double *n
     dim3 grid((unsigned)blocks, (unsigned)K), block(256);
     if (form == HSD_FORM_FP64)
         hipLaunchKernelGGL(k_direct_gen<HSD_FORM_FP64>, grid, block, 0, st, mp.A, mp.nA, mp.B, mp.nB,
-                           nodes, n, tau, partial);
+                           nodes, n, i_begin, i_count, tau, partial);
     else
         hipLaunchKernelGGL(k_direct_gen<HSD_FORM_MIXED>, grid, block, 0, st, mp.A, mp.nA, mp.B, mp.nB,
-                           nodes, n, tau, partial);
+                           nodes, n, i_begin, i_count, tau, partial);
     HSD_HIP_TRY(hipGetLastError());
     return HSD_OK;
+}
+
+hsd_status launch_direct_gen(hipStream_t st, const MeshPair &mp, const double *nodes, int64_t n, int form,
+                             double tau, int K, double2 *partial)
+{
+    return launch_direct_gen_range(st, mp, nodes, n, form, tau, K, 0, n, partial);
 }
 
 int64_t finalize_blocks(int64_t n) { return (n + kFinBlock - 1) / kFinBlock; }

@@ -159,6 +159,14 @@ hsd_status launch_direct_sp(hipStream_t st, const MeshPair &mp, const hsd_rule *
                             int form, double tau, int K, double2 *partial);
 hsd_status launch_direct_gen(hipStream_t st, const MeshPair &mp, const double *nodes,
                              int64_t n, int form, double tau, int K, double2 *partial);
+hsd_status launch_direct_sp_range(hipStream_t st, const MeshPair &mp, const hsd_rule *rule,
+                                  int form, double tau, int K, int64_t d_begin, int64_t d_count,
+                                  double2 *partial);
+hsd_status launch_direct_gen_range(hipStream_t st, const MeshPair &mp, const double *nodes,
+                                   int64_t n, int form, double tau, int K, int64_t i_begin,
+                                   int64_t i_count, double2 *partial);
+hsd_status create_mesh_on(hsd_ctx *ctx, hipStream_t st, const double *verts, int64_t nv,
+                          const int32_t *tris, int64_t nt, int32_t mem_kind, hsd_mesh **out);
 hsd_status launch_finalize(hipStream_t st, const hsd_rule *rule, const double *wtab,
                            const double *nutab, const double2 *partial, int K, int64_t n,
                            bool sphere_target, double2 *resid_out, double *block_out,

@@ -198,8 +198,9 @@ HSD_HD void sort3(T x0, T x1, T x2, T &lo, T &mid, T &hi)
 }
 
 // Power series of the second divided difference of exp at (i a, 0, -i b)
-// (a, b >= 0, a + b < tau <= 0.05): sum_n (-i)^n H_n / (n+2)!,
-// H_n = sum_{m<=n} (-a)^m b^(n-m).  Terms beyond n = 9 are below 1e-21.
+// (a, b >= 0): sum_n (-i)^n H_n / (n+2)!, H_n = sum_{m<=n} (-a)^m b^(n-m),
+// summed through n = 9; the first omitted term is below 11 G^10 / 12! with
+// G = a + b (4e-27 at G = 0.01, 2e-11 at G = 0.5).
 template <typename T>
 HSD_HD void dd2_series(T a, T b, T &re, T &im)
 {
