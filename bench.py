@@ -47,22 +47,20 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (packed); 78.6 without packed F
 
 def flops_per_pair_fp64(spec) -> float:
     """Algorithmic FP64 FLOPs (FMA = 2) per triangle-node pair of the
-    spherical-product FP64 kernel, counted from its source.
+    wave-per-direction FP64 kernel (16-node panels), counted from its source.
 
-    per node : 3 phase products (6 each) + closed-branch numerators (8)
-               + radius (1) + complex multiply-accumulate (8)          = 35
-    per panel: 3 panel-centre phase updates (18), shared by 2 nodes      =  9
-    per (triangle, lane): 3 dot products (15), gaps (3), 3 reciprocals
-               (27), scale factors (7), 6 FP64 sin/cos (43 each) plus 3
-               more for lane groups not starting at panel 0, 3 squarings
-               (18), 6 argument products                                 = 334 (+132)
-    The per-(triangle, lane) part is spread over the lane's 2*PG nodes.
+    consumer, per node: 3 phase products (6 each) + closed-branch numerators
+        (8) + radius (1) + complex multiply-accumulate (8)            = 35
+    producer, per (triangle, lane), done once per batch of 8 triangles:
+        dot products, gaps, reciprocal (28) + (2 + PG) x 3 FP64 sin/cos
+        (43 each) + their arguments (3 (2 + PG)) + scale factors (20/8)
+    A lane owns 2*PG nodes, so per pair:
+        35 + [28 + 3(2+PG)(43+1) + 2.5] / 8 / (2 PG).
     """
     P = spec["n_panels"]
-    PG = 4 if P % 4 == 0 else (2 if P % 2 == 0 else 1)
-    groups = P // PG
-    per_tl = 334.0 + 132.0 * (groups - 1) / groups
-    return 35.0 + 9.0 + per_tl / (2 * PG)
+    PG = 2 if P % 16 == 0 else 1
+    producer = 28.0 + 3 * (2 + PG) * 44.0 + 2.5
+    return 35.0 + producer / 8.0 / (2 * PG)
 
 
 def main():
@@ -134,7 +132,7 @@ def main():
     achieved = flop_pair * pairs / (kern_ms * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                       "kernel": "k_direct_sp_f64", "kernel_ms": kern_ms,
+                       "kernel": "k_direct_wave<FP64>", "kernel_ms": kern_ms,
                        "flops_per_pair": flop_pair}
     if not args.no_mixed:
         mixed = hsd.Params(s=1.0, form="mixed")

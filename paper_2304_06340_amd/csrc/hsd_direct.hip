@@ -530,9 +530,14 @@ int choose_k_splits_sp(const hsd_rule *rule, int64_t nt, int form, int num_cu, i
 {
     if (nt <= 0) return 1;
     if (req > 0) return (int)std::min<int64_t>(req, std::max<int64_t>(1, nt));
-    const int PG = pick_pg(rule->sp.P, form);
-    const int64_t lanes = (int64_t)(rule->sp.P / PG) * rule->n_dir * (rule->sp.n / 2);
-    const int64_t waves = (lanes + 63) / 64;
+    int64_t waves;
+    if (wave_kernel_applies(rule)) {
+        waves = wave_count(rule);
+    } else {
+        const int PG = pick_pg(rule->sp.P, form);
+        const int64_t lanes = (int64_t)(rule->sp.P / PG) * rule->n_dir * (rule->sp.n / 2);
+        waves = (lanes + 63) / 64;
+    }
     // aim for >= 8 waves per SIMD (4 SIMDs per CU) and >= 64 triangles per split
     const int64_t target = (int64_t)num_cu * 4 * 8;
     int64_t K = (target + waves - 1) / waves;
@@ -581,6 +586,7 @@ static hsd_status launch_sp_pg(hipStream_t st, const MeshPair &mp, const hsd_rul
 hsd_status launch_direct_sp_range(hipStream_t st, const MeshPair &mp, const hsd_rule *rule, int form,
                                   double tau, int K, int64_t d_begin, int64_t d_count, double2 *partial)
 {
+    if (wave_kernel_applies(rule)) return launch_direct_wave(st, mp, rule, form, tau, K, d_begin, d_count, partial);
     switch (pick_pg(rule->sp.P, form)) {
     case 8: return launch_sp_pg<8>(st, mp, rule, form, tau, K, d_begin, d_count, partial);
     case 4: return launch_sp_pg<4>(st, mp, rule, form, tau, K, d_begin, d_count, partial);

@@ -1,0 +1,461 @@
+// hsd_direct_wave.hip -- direct-sum kernel with one wavefront per direction
+// for spherical-product rules with 16 Gauss-Legendre nodes per panel.
+//
+// Same arithmetic as the lane bodies of hsd_direct.hip (exact triangle
+// transform as J * e[z0,z1,z2], sorted phases, closed branch above tau,
+// series below, r^2-scaled accumulation), organised so the per-(triangle,
+// direction) work is shared by the whole wave instead of recomputed by
+// every lane:
+//
+//   * a wave owns one direction n and 8*PG consecutive panels; lane
+//     (k, g) = (lane % 8, lane / 8) owns the node pair m_p +- h x_k of its
+//     PG panels p = w0 + g*PG + pl (2*PG nodes);
+//   * triangles are processed in batches of 8.  Producer step: lane
+//     (t, j) = (lane / 8, lane % 8) computes, for triangle t of the batch,
+//     exp(-i h x_j c), exp(-i (h - h x_j) c) (the small-radius node of panel
+//     0, evaluated directly to keep relative accuracy) and the panel-centre
+//     phases exp(-i m_p c) of panels w0 + j*PG .. w0 + j*PG + PG-1, for the
+//     three constants c = theta_mid, a/2, b/2 of the triangle and direction,
+//     and stores them with the triangle's scale factors in LDS;
+//   * consumer step: every lane forms its node phases by one complex product
+//     per constant and node and accumulates, reading the batch from LDS.
+//
+// Per-lane sums use FP64 tiles of 32 triangles merged into running totals
+// (mixed: FP32 tiles); K triangle splits on grid.y as in hsd_direct.hip.
+#include <type_traits>
+#include <vector>
+
+#include "hsd_internal.hpp"
+#include "hsd_math.hpp"
+
+namespace hsd {
+
+namespace wv {
+
+constexpr int kTB = 8;        // triangles per batch
+constexpr int kNH = 8;        // node pairs per panel (16 GL nodes)
+constexpr int kTileBatches = 4;   // batches per FP64 tile sum (32 triangles)
+constexpr double kGapFloor = 1e-150;
+constexpr double kGapFloor32 = 1e-18;
+constexpr double kMixedTau = 0.05;
+
+struct Scal64 { double Ka, Kb, rthr, ac, bc, J, pad0, pad1; };
+struct Scal32 { double rthr, J; float Ka, Kb, ac, bc; };
+
+template <int PG> struct Batch64 {
+    Scal64 sc[kTB];
+    cs64 Bk[kTB][kNH][3];
+    cs64 P0[kTB][kNH][3];
+    cs64 Cp[kTB][kNH * PG][3];
+};
+template <int PG> struct Batch32 {
+    Scal32 sc[kTB];
+    cs32 Bk[kTB][kNH][3];
+    cs32 P0[kTB][kNH][3];
+    cs32 Cp[kTB][kNH * PG][3];
+};
+
+// Per-(triangle, direction) constants: sorted gaps (floored), theta_mid and
+// the closed-branch scale factors.
+struct TriDir {
+    double tmid, ac, bc, iG, J;
+};
+
+HSD_HD TriDir tri_dir(const TriRec &T, double J, double nx, double ny, double nz, double floor)
+{
+    const double t0 = __builtin_fma(nx, T.p0[0], __builtin_fma(ny, T.p0[1], nz * T.p0[2]));
+    const double d1 = __builtin_fma(nx, T.e1[0], __builtin_fma(ny, T.e1[1], nz * T.e1[2]));
+    const double d2 = __builtin_fma(nx, T.e2[0], __builtin_fma(ny, T.e2[1], nz * T.e2[2]));
+    double lo, mid, hi;
+    sort3(0.0, d1, d2, lo, mid, hi);
+    TriDir r;
+    r.ac = fmax(mid - lo, floor);
+    r.bc = fmax(hi - mid, floor);
+    r.tmid = t0 + mid;
+    r.iG = rcp64(r.ac + r.bc);
+    r.J = J;
+    return r;
+}
+
+// Producer, FP64: part j of a triangle's batch entry.
+template <int PG>
+HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
+                      Scal64 *sc, cs64 Bk[3], cs64 P0[3], cs64 Cp[PG][3])
+{
+    const double fr[3] = {td.tmid, 0.5 * td.ac, 0.5 * td.bc};
+    const double hx = hx_tab[j];
+    const double r0 = h - hx;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Bk[c] = sincos64(hx * fr[c]);
+        P0[c] = sincos64(r0 * fr[c]);
+#pragma unroll
+        for (int q = 0; q < PG; ++q) Cp[q][c] = sincos64((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c]);
+    }
+    if (sc) {
+        sc->Ka = 2.0 * td.J * rcp64(td.ac) * td.iG;
+        sc->Kb = 2.0 * td.J * rcp64(td.bc) * td.iG;
+        sc->rthr = tau * td.iG;
+        sc->ac = td.ac;
+        sc->bc = td.bc;
+        sc->J = td.J;
+    }
+}
+
+// Consumer, FP64: one triangle into the lane's 2*PG slots (slot 2*pl + sg).
+template <int PG>
+HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 P0[3], const cs64 (*Cp)[3], double h,
+                      double hx, int pfirst, double *acc_re, double *acc_im)
+{
+#pragma unroll
+    for (int pl = 0; pl < PG; ++pl) {
+        const int p = pfirst + pl;
+        const double m = (double)(2 * p + 1) * h;
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            const int slot = 2 * pl + sg;
+            const double r = sg == 0 ? m + hx : m - hx;
+            cs64 E[3];
+            const bool direct = (sg == 1) && (p == 0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const cs64 prod = sg == 0 ? pmul(Cp[pl][c], Bk[c]) : pmulc(Cp[pl][c], Bk[c]);
+                E[c] = direct ? P0[c] : prod;
+            }
+            const double Pv = sc.Kb * E[2].s;
+            const double Pu = sc.Ka * E[1].s;
+            double Yr = __builtin_fma(Pv, E[2].s, Pu * E[1].s);
+            double Xr = __builtin_fma(Pv, E[2].c, -Pu * E[1].c);
+            if (r < sc.rthr) {
+                double fre, fim;
+                dd2_series(r * sc.ac, r * sc.bc, fre, fim);
+                const double r2J = r * r * sc.J;
+                Yr = r2J * fre;
+                Xr = r2J * fim;
+            }
+            acc_re[slot] += __builtin_fma(E[0].c, Yr, E[0].s * Xr);
+            acc_im[slot] += __builtin_fma(E[0].c, Xr, -E[0].s * Yr);
+        }
+    }
+}
+
+// Producer, mixed: FP32 phases from FP64-reduced angles.
+template <int PG>
+HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
+                      Scal32 *sc, cs32 Bk[3], cs32 P0[3], cs32 Cp[PG][3])
+{
+    const double fr[3] = {td.tmid, 0.5 * td.ac, 0.5 * td.bc};
+    const double hx = hx_tab[j];
+    const double r0 = h - hx;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Bk[c] = sincos32_acc(hx * fr[c]);
+        P0[c] = sincos32_acc(r0 * fr[c]);
+#pragma unroll
+        for (int q = 0; q < PG; ++q) Cp[q][c] = sincos32_acc((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c]);
+    }
+    if (sc) {
+        sc->Ka = (float)(2.0 * td.J * rcp64(td.ac) * td.iG);
+        sc->Kb = (float)(2.0 * td.J * rcp64(td.bc) * td.iG);
+        sc->rthr = fmax(tau, kMixedTau) * td.iG;
+        sc->ac = (float)td.ac;
+        sc->bc = (float)td.bc;
+        sc->J = td.J;
+    }
+}
+
+template <int PG>
+HSD_HD void consume32(const Scal32 &sc, const cs32 Bk[3], const cs32 P0[3], const cs32 (*Cp)[3], double h,
+                      double hx, int pfirst, float *acc_re, float *acc_im)
+{
+#pragma unroll
+    for (int pl = 0; pl < PG; ++pl) {
+        const int p = pfirst + pl;
+        const double m = (double)(2 * p + 1) * h;
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            const int slot = 2 * pl + sg;
+            const double rd = sg == 0 ? m + hx : m - hx;
+            const float r = (float)rd;
+            cs32 E[3];
+            const bool direct = (sg == 1) && (p == 0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const cs32 prod = sg == 0 ? pmul(Cp[pl][c], Bk[c]) : pmulc(Cp[pl][c], Bk[c]);
+                E[c] = direct ? P0[c] : prod;
+            }
+            float Yr, Xr;
+            if (rd < sc.rthr) {
+                float fre, fim;
+                dd2_series(r * sc.ac, r * sc.bc, fre, fim);
+                const float r2J = (float)(rd * rd * sc.J);
+                Yr = r2J * fre;
+                Xr = r2J * fim;
+            } else {
+                const float Pv = sc.Kb * E[2].s;
+                const float Pu = sc.Ka * E[1].s;
+                Yr = __builtin_fmaf(Pv, E[2].s, Pu * E[1].s);
+                Xr = __builtin_fmaf(Pv, E[2].c, -Pu * E[1].c);
+            }
+            acc_re[slot] += __builtin_fmaf(E[0].c, Yr, E[0].s * Xr);
+            acc_im[slot] += __builtin_fmaf(E[0].c, Xr, -E[0].s * Yr);
+        }
+    }
+}
+
+HSD_HD const TriRec *tri_at(const TriRec *A, int64_t nA, const TriRec *B, int64_t gi, double &J)
+{
+    const bool inA = gi < nA;
+    const TriRec *rp = inA ? (A + gi) : (B + (gi - nA));
+    J = inA ? rp->J : -rp->J;
+    return rp;
+}
+
+} // namespace wv
+
+// ---------------------------------------------------------------------------
+// kernel: 4 waves per block, one direction (and panel window) per wave
+// ---------------------------------------------------------------------------
+template <int PG, int FORM>
+__global__ __launch_bounds__(256) void k_direct_wave(
+    const TriRec *__restrict__ A, int64_t nA, const TriRec *__restrict__ B, int64_t nB,
+    const double *__restrict__ dirs, const double *__restrict__ hx_tab, int64_t d_begin, int64_t d_count,
+    int P, double h, double tau, int64_t N, double2 *__restrict__ partial)
+{
+    using namespace wv;
+    constexpr int NS = 2 * PG;
+    constexpr bool F64 = FORM == HSD_FORM_FP64;
+    __shared__ typename std::conditional<F64, Batch64<PG>, Batch32<PG>>::type lds[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wpd = P / (kNH * PG);                 // waves per direction
+    const int64_t gw = (int64_t)blockIdx.x * 4 + w;
+    const bool valid = gw < d_count * wpd;
+    const int64_t GW = valid ? gw : 0;
+    const int64_t d = d_begin + GW / wpd;
+    const int w0 = (int)(GW % wpd) * kNH * PG;       // first panel of the wave
+    const double nx = dirs[3 * d], ny = dirs[3 * d + 1], nz = dirs[3 * d + 2];
+    const int k = lane & 7, g = lane >> 3;             // consumer roles
+    const int pt = lane >> 3, pj = lane & 7;           // producer roles
+    const double hx = hx_tab[k];
+    const int pfirst = w0 + g * PG;
+    auto &L = lds[w];
+
+    const int64_t ntot = nA + nB;
+    const int K = gridDim.y;
+    const int64_t t_begin = ntot * blockIdx.y / K;
+    const int64_t t_end = ntot * (blockIdx.y + 1) / K;
+
+    double tot_re[NS], tot_im[NS];
+    using acc_t = typename std::conditional<F64, double, float>::type;
+    acc_t acc_re[NS], acc_im[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) { tot_re[i] = 0.0; tot_im[i] = 0.0; acc_re[i] = 0; acc_im[i] = 0; }
+
+    int nb = 0;
+    for (int64_t tb = t_begin; tb < t_end; tb += kTB) {
+        const int nvalid = (int)((t_end - tb) < kTB ? (t_end - tb) : kTB);
+        {   // produce
+            const int64_t gi = tb + (pt < nvalid ? pt : 0);
+            double J;
+            const TriRec *rp = wv::tri_at(A, nA, B, gi, J);
+            const TriDir td = tri_dir(*rp, J, nx, ny, nz, F64 ? kGapFloor : kGapFloor32);
+            if constexpr (F64)
+                produce64<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
+                              L.P0[pt][pj], &L.Cp[pt][pj * PG]);
+            else
+                produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
+                              L.P0[pt][pj], &L.Cp[pt][pj * PG]);
+        }
+        __syncthreads();
+        for (int t = 0; t < nvalid; ++t) {
+            if constexpr (F64)
+                consume64<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx, pfirst, acc_re, acc_im);
+            else
+                consume32<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx, pfirst, acc_re, acc_im);
+        }
+        __syncthreads();
+        if (++nb == kTileBatches) {
+            nb = 0;
+#pragma unroll
+            for (int i = 0; i < NS; ++i) {
+                tot_re[i] += (double)acc_re[i];
+                tot_im[i] += (double)acc_im[i];
+                acc_re[i] = 0;
+                acc_im[i] = 0;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) { tot_re[i] += (double)acc_re[i]; tot_im[i] += (double)acc_im[i]; }
+    if (!valid) return;
+    double2 *out = partial + (int64_t)blockIdx.y * N + d * (int64_t)(P * 2 * kNH);
+#pragma unroll
+    for (int pl = 0; pl < PG; ++pl) {
+        const int p = pfirst + pl;
+        const double m = (double)(2 * p + 1) * h;
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            const int slot = 2 * pl + sg;
+            const double r = sg == 0 ? m + hx : m - hx;
+            const double inv = 1.0 / (r * r);
+            const int jn = sg == 0 ? kNH + k : kNH - 1 - k;
+            out[(int64_t)p * (2 * kNH) + jn] = make_double2(tot_re[slot] * inv, tot_im[slot] * inv);
+        }
+    }
+}
+
+bool wave_kernel_applies(const hsd_rule *rule)
+{
+    return rule->kind == HSD_RULE_SPHERICAL_PRODUCT && rule->sp.n == 16 && rule->sp.P % wv::kNH == 0;
+}
+
+static int wave_pg(const hsd_rule *rule) { return rule->sp.P % (2 * wv::kNH) == 0 ? 2 : 1; }
+
+int64_t wave_count(const hsd_rule *rule)
+{
+    const int PG = wave_pg(rule);
+    return rule->n_dir * (rule->sp.P / (wv::kNH * PG));
+}
+
+template <int PG>
+static hsd_status launch_wave_pg(hipStream_t st, const MeshPair &mp, const hsd_rule *rule, int form, double tau,
+                                 int K, int64_t d_begin, int64_t d_count, double2 *partial)
+{
+    const int wpd = rule->sp.P / (wv::kNH * PG);
+    const int64_t waves = d_count * wpd;
+    const int64_t blocks = (waves + 3) / 4;
+    if (waves <= 0) return HSD_OK;
+    if (blocks > INT32_MAX || K > 65535) {
+        set_error("direct_wave: grid too large");
+        return HSD_EINVAL;
+    }
+    dim3 grid((unsigned)blocks, (unsigned)K), block(256);
+    if (form == HSD_FORM_FP64)
+        hipLaunchKernelGGL((k_direct_wave<PG, HSD_FORM_FP64>), grid, block, 0, st, mp.A, mp.nA, mp.B, mp.nB,
+                           rule->d_dirs.as<const double>(), rule->d_hx.as<const double>(), d_begin, d_count,
+                           rule->sp.P, rule->sp.h, tau, rule->n_nodes, partial);
+    else
+        hipLaunchKernelGGL((k_direct_wave<PG, HSD_FORM_MIXED>), grid, block, 0, st, mp.A, mp.nA, mp.B, mp.nB,
+                           rule->d_dirs.as<const double>(), rule->d_hx.as<const double>(), d_begin, d_count,
+                           rule->sp.P, rule->sp.h, tau, rule->n_nodes, partial);
+    HSD_HIP_TRY(hipGetLastError());
+    return HSD_OK;
+}
+
+hsd_status launch_direct_wave(hipStream_t st, const MeshPair &mp, const hsd_rule *rule, int form, double tau,
+                              int K, int64_t d_begin, int64_t d_count, double2 *partial)
+{
+    return wave_pg(rule) == 2 ? launch_wave_pg<2>(st, mp, rule, form, tau, K, d_begin, d_count, partial)
+                              : launch_wave_pg<1>(st, mp, rule, form, tau, K, d_begin, d_count, partial);
+}
+
+// ---------------------------------------------------------------------------
+// host emulation of one direction (self checks)
+// ---------------------------------------------------------------------------
+template <int PG, bool F64>
+static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, double nz, const double *hx_tab,
+                          int P, double h, double tau, double *out /* [P*16*2] */)
+{
+    using namespace wv;
+    constexpr int NS = 2 * PG;
+    const int wpd = P / (kNH * PG);
+    std::vector<Batch64<PG>> b64(1);
+    std::vector<Batch32<PG>> b32(1);
+    for (int wi = 0; wi < wpd; ++wi) {
+        const int w0 = wi * kNH * PG;
+        std::vector<double> tre(64 * NS, 0.0), tim(64 * NS, 0.0);
+        std::vector<double> are(64 * NS, 0.0), aim(64 * NS, 0.0);
+        std::vector<float> fre(64 * NS, 0.0f), fim(64 * NS, 0.0f);
+        int nb = 0;
+        for (int64_t tb = 0; tb < nA; tb += kTB) {
+            const int nvalid = (int)std::min<int64_t>(kTB, nA - tb);
+            for (int lane = 0; lane < 64; ++lane) {
+                const int pt = lane >> 3, pj = lane & 7;
+                double J;
+                const TriRec *rp = wv::tri_at(A, nA, nullptr, tb + (pt < nvalid ? pt : 0), J);
+                const TriDir td = tri_dir(*rp, J, nx, ny, nz, F64 ? kGapFloor : kGapFloor32);
+                if (F64) {
+                    auto &L = b64[0];
+                    produce64<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
+                                  L.P0[pt][pj], &L.Cp[pt][pj * PG]);
+                } else {
+                    auto &L = b32[0];
+                    produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
+                                  L.P0[pt][pj], &L.Cp[pt][pj * PG]);
+                }
+            }
+            for (int lane = 0; lane < 64; ++lane) {
+                const int k = lane & 7, g = lane >> 3;
+                for (int t = 0; t < nvalid; ++t) {
+                    if (F64) {
+                        auto &L = b64[0];
+                        consume64<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx_tab[k], w0 + g * PG,
+                                      &are[lane * NS], &aim[lane * NS]);
+                    } else {
+                        auto &L = b32[0];
+                        consume32<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx_tab[k], w0 + g * PG,
+                                      &fre[lane * NS], &fim[lane * NS]);
+                    }
+                }
+            }
+            if (++nb == kTileBatches) {
+                nb = 0;
+                for (int i = 0; i < 64 * NS; ++i) {
+                    tre[i] += F64 ? are[i] : (double)fre[i];
+                    tim[i] += F64 ? aim[i] : (double)fim[i];
+                    are[i] = aim[i] = 0.0;
+                    fre[i] = fim[i] = 0.0f;
+                }
+            }
+        }
+        for (int lane = 0; lane < 64; ++lane) {
+            const int k = lane & 7, g = lane >> 3;
+            for (int pl = 0; pl < PG; ++pl)
+                for (int sg = 0; sg < 2; ++sg) {
+                    const int i = lane * NS + 2 * pl + sg;
+                    const double re = tre[i] + (F64 ? are[i] : (double)fre[i]);
+                    const double im = tim[i] + (F64 ? aim[i] : (double)fim[i]);
+                    const int p = w0 + g * PG + pl;
+                    const double m = (double)(2 * p + 1) * h;
+                    const double r = sg == 0 ? m + hx_tab[k] : m - hx_tab[k];
+                    const int jn = sg == 0 ? kNH + k : kNH - 1 - k;
+                    const int64_t q = (int64_t)p * 16 + jn;
+                    out[2 * q] = re / (r * r);
+                    out[2 * q + 1] = im / (r * r);
+                }
+        }
+    }
+}
+
+void build_tri_records(const double *verts, const int32_t *tris, int64_t nt, TriRec *rec);
+
+} // namespace hsd
+
+extern "C" {
+
+// mu^ at every node of a spherical product rule (n = 16 per panel, P a
+// multiple of 8) through the wave kernel's producer/consumer bodies on the
+// CPU (self checks only).  out[n_dir * P * 16 * 2].
+int hsd__host_transform_wave(const double *verts, const int32_t *tris, int64_t nt, const double *dirs,
+                             int64_t n_dir, const double *hx_tab, int P, double h, double tau, int form, double *out)
+{
+    using namespace hsd;
+    if (P % 8 != 0) return -1;
+    std::vector<TriRec> rec((size_t)nt);
+    build_tri_records(verts, tris, nt, rec.data());
+    const bool pg2 = P % 16 == 0;
+    for (int64_t d = 0; d < n_dir; ++d) {
+        double *o = out + 2 * d * (int64_t)P * 16;
+        const double nx = dirs[3 * d], ny = dirs[3 * d + 1], nz = dirs[3 * d + 2];
+        if (form == HSD_FORM_FP64) {
+            if (pg2) host_wave_dir<2, true>(rec.data(), nt, nx, ny, nz, hx_tab, P, h, tau, o);
+            else host_wave_dir<1, true>(rec.data(), nt, nx, ny, nz, hx_tab, P, h, tau, o);
+        } else {
+            if (pg2) host_wave_dir<2, false>(rec.data(), nt, nx, ny, nz, hx_tab, P, h, tau, o);
+            else host_wave_dir<1, false>(rec.data(), nt, nx, ny, nz, hx_tab, P, h, tau, o);
+        }
+    }
+    return 0;
+}
+
+} // extern "C"

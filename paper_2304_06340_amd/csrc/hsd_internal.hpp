@@ -176,6 +176,11 @@ hsd_status launch_final_reduce(hipStream_t st, const double *block_in, int64_t n
 hsd_status launch_sum_partials(hipStream_t st, const double2 *partial, int K, int64_t n,
                                double2 *out);
 int64_t finalize_blocks(int64_t n);
+// wave-per-direction kernel (hsd_direct_wave.hip) for 16-node panels
+bool wave_kernel_applies(const hsd_rule *rule);
+int64_t wave_count(const hsd_rule *rule);
+hsd_status launch_direct_wave(hipStream_t st, const MeshPair &mp, const hsd_rule *rule, int form,
+                              double tau, int K, int64_t d_begin, int64_t d_count, double2 *partial);
 int choose_k_splits_sp(const hsd_rule *rule, int64_t nt, int form, int num_cu, int req);
 int choose_k_splits_gen(int64_t n, int64_t nt, int num_cu, int req);
 

@@ -135,3 +135,53 @@ def test_gen_lane_matches_oracle(orc, form):
         assert np.all(err <= mu_tol(v, f, nodes, 40.0)), err.max()
     else:
         assert err.max() <= 3e-6 * _area(v, f)
+
+
+def host_wave(v, f, spec, form=0, tau=1e-2):
+    L = _lib()
+    L.hsd__host_transform_wave.argtypes = [dp, C.c_void_p, C.c_int64, dp, C.c_int64, dp, C.c_int,
+                                           C.c_double, C.c_double, C.c_int, dp]
+    P, n, nc, nphi, R = spec["n_panels"], spec["n_per_panel"], spec["n_cos"], spec["n_phi"], spec["r_max"]
+    assert n == 16 and P % 8 == 0
+    x, _ = np.polynomial.legendre.leggauss(n)
+    mu, _ = np.polynomial.legendre.leggauss(nc)
+    phi = 2 * np.pi * np.arange(nphi) / nphi
+    st = np.sqrt(1 - mu * mu)
+    dirs = np.ascontiguousarray(np.stack([(st[:, None] * np.cos(phi)).ravel(),
+                                          (st[:, None] * np.sin(phi)).ravel(),
+                                          np.repeat(mu, nphi)], axis=1))
+    h = R / P / 2
+    hx = np.ascontiguousarray(h * x[n // 2:])
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    f = np.ascontiguousarray(f, dtype=np.int32)
+    out = np.zeros(2 * len(dirs) * P * n)
+    assert L.hsd__host_transform_wave(_p(v), f.ctypes.data, len(f), _p(dirs), len(dirs), _p(hx), P, h, tau,
+                                      form, _p(out)) == 0
+    return out[0::2] + 1j * out[1::2]
+
+
+@pytest.mark.parametrize("spec", [
+    dict(r_max=64.0, n_panels=8, n_per_panel=16, n_cos=3, n_phi=4),     # one panel per lane
+    dict(r_max=96.0, n_panels=16, n_per_panel=16, n_cos=2, n_phi=3),    # two panels per lane
+    dict(r_max=64.0, n_panels=32, n_per_panel=16, n_cos=2, n_phi=2),    # two waves per direction
+])
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("perturb", [True, False])
+def test_wave_kernel_bodies_match_oracle(orc, spec, form, perturb):
+    """Producer/consumer bodies of the wave-per-direction kernel, run on the
+    CPU lane by lane, against the oracle at every rule node (ragged last
+    triangle batch: 80 triangles = 10 batches of 8; 20 triangles: ragged)."""
+    rng = np.random.default_rng(9)
+    v, f = icosphere(1)
+    if perturb:
+        v = rotate(perturb_radial(v, 0.01, rng), random_rotation(rng))
+    f = f[:76]       # ragged batch
+    got = host_wave(v, f, spec, form)
+    o = orc.spherical_product_rule(**spec)
+    ref = orc.transform(v, f, o.nodes)
+    err = np.abs(got - ref)
+    if form == 0:
+        assert np.all(err <= mu_tol(v, f, o.nodes)), err.max()
+    else:
+        assert np.all(np.isfinite(got))
+        assert err.max() <= 2e-5 * _area(v, f)
