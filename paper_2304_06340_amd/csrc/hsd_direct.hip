@@ -167,9 +167,9 @@ HSD_HD void sp_lane_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t 
 #pragma unroll
     for (int i = 0; i < NS; ++i) { tot_re[i] = 0.0; tot_im[i] = 0.0; }
     for (int64_t t0i = t_begin; t0i < t_end; t0i += kTile) {
-        float acc_re[NS], acc_im[NS];
+        double acc_re[NS], acc_im[NS];
 #pragma unroll
-        for (int i = 0; i < NS; ++i) { acc_re[i] = 0.0f; acc_im[i] = 0.0f; }
+        for (int i = 0; i < NS; ++i) { acc_re[i] = 0.0; acc_im[i] = 0.0; }
         const int64_t tile_end = (t0i + kTile < t_end) ? t0i + kTile : t_end;
         for (int64_t gi = t0i; gi < tile_end; ++gi) {
             double J;
@@ -229,15 +229,15 @@ HSD_HD void sp_lane_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t 
                         Yr = __builtin_fmaf(Pv, Ev.s, Pu * Eu.s);
                         Xr = __builtin_fmaf(Pv, Ev.c, -Pu * Eu.c);
                     }
-                    acc_re[slot] += __builtin_fmaf(E1.c, Yr, E1.s * Xr);
-                    acc_im[slot] += __builtin_fmaf(E1.c, Xr, -E1.s * Yr);
+                    acc_re[slot] += (double)__builtin_fmaf(E1.c, Yr, E1.s * Xr);
+                    acc_im[slot] += (double)__builtin_fmaf(E1.c, Xr, -E1.s * Yr);
                 }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) Cp[c] = pmul(Cp[c], S[c]);
             }
         }
 #pragma unroll
-        for (int i = 0; i < NS; ++i) { tot_re[i] += (double)acc_re[i]; tot_im[i] += (double)acc_im[i]; }
+        for (int i = 0; i < NS; ++i) { tot_re[i] += acc_re[i]; tot_im[i] += acc_im[i]; }
     }
 }
 
@@ -293,7 +293,7 @@ HSD_HD void gen_node_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t
 {
     double tot_re = 0.0, tot_im = 0.0;
     for (int64_t t0i = t_begin; t0i < t_end; t0i += kTile) {
-        float acc_re = 0.0f, acc_im = 0.0f;
+        double acc_re = 0.0, acc_im = 0.0;
         const int64_t tile_end = (t0i + kTile < t_end) ? t0i + kTile : t_end;
         for (int64_t gi = t0i; gi < tile_end; ++gi) {
             double J;
@@ -322,11 +322,11 @@ HSD_HD void gen_node_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t
                 Yr = __builtin_fmaf(Pv, Ev.s, Pu * Eu.s);
                 Xr = __builtin_fmaf(Pv, Ev.c, -Pu * Eu.c);
             }
-            acc_re += __builtin_fmaf(E1.c, Yr, E1.s * Xr);
-            acc_im += __builtin_fmaf(E1.c, Xr, -E1.s * Yr);
+            acc_re += (double)__builtin_fmaf(E1.c, Yr, E1.s * Xr);
+            acc_im += (double)__builtin_fmaf(E1.c, Xr, -E1.s * Yr);
         }
-        tot_re += (double)acc_re;
-        tot_im += (double)acc_im;
+        tot_re += acc_re;
+        tot_im += acc_im;
     }
     out_re = tot_re;
     out_im = tot_im;

@@ -21,7 +21,8 @@
 //     per constant and node and accumulates, reading the batch from LDS.
 //
 // Per-lane sums use FP64 tiles of 32 triangles merged into running totals
-// (mixed: FP32 tiles); K triangle splits on grid.y as in hsd_direct.hip.
+// (the mixed form adds its FP32 contributions in FP64 too); K triangle
+// splits on grid.y as in hsd_direct.hip.
 #include <type_traits>
 #include <vector>
 
@@ -164,9 +165,12 @@ HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, i
     }
 }
 
+// Consumer, mixed: FP32 node arithmetic; each contribution is added in FP64
+// (an FP32 tile sum of the nearly coherent terms at small |xi| would lose
+// ~sqrt(tile) eps32 of the whole transform).
 template <int PG>
 HSD_HD void consume32(const Scal32 &sc, const cs32 Bk[3], const cs32 P0[3], const cs32 (*Cp)[3], double h,
-                      double hx, int pfirst, float *acc_re, float *acc_im)
+                      double hx, int pfirst, double *acc_re, double *acc_im)
 {
 #pragma unroll
     for (int pl = 0; pl < PG; ++pl) {
@@ -197,8 +201,8 @@ HSD_HD void consume32(const Scal32 &sc, const cs32 Bk[3], const cs32 P0[3], cons
                 Yr = __builtin_fmaf(Pv, E[2].s, Pu * E[1].s);
                 Xr = __builtin_fmaf(Pv, E[2].c, -Pu * E[1].c);
             }
-            acc_re[slot] += __builtin_fmaf(E[0].c, Yr, E[0].s * Xr);
-            acc_im[slot] += __builtin_fmaf(E[0].c, Xr, -E[0].s * Yr);
+            acc_re[slot] += (double)__builtin_fmaf(E[0].c, Yr, E[0].s * Xr);
+            acc_im[slot] += (double)__builtin_fmaf(E[0].c, Xr, -E[0].s * Yr);
         }
     }
 }
@@ -246,8 +250,7 @@ __global__ __launch_bounds__(256) void k_direct_wave(
     const int64_t t_end = ntot * (blockIdx.y + 1) / K;
 
     double tot_re[NS], tot_im[NS];
-    using acc_t = typename std::conditional<F64, double, float>::type;
-    acc_t acc_re[NS], acc_im[NS];
+    double acc_re[NS], acc_im[NS];
 #pragma unroll
     for (int i = 0; i < NS; ++i) { tot_re[i] = 0.0; tot_im[i] = 0.0; acc_re[i] = 0; acc_im[i] = 0; }
 
@@ -278,15 +281,15 @@ __global__ __launch_bounds__(256) void k_direct_wave(
             nb = 0;
 #pragma unroll
             for (int i = 0; i < NS; ++i) {
-                tot_re[i] += (double)acc_re[i];
-                tot_im[i] += (double)acc_im[i];
-                acc_re[i] = 0;
-                acc_im[i] = 0;
+                tot_re[i] += acc_re[i];
+                tot_im[i] += acc_im[i];
+                acc_re[i] = 0.0;
+                acc_im[i] = 0.0;
             }
         }
     }
 #pragma unroll
-    for (int i = 0; i < NS; ++i) { tot_re[i] += (double)acc_re[i]; tot_im[i] += (double)acc_im[i]; }
+    for (int i = 0; i < NS; ++i) { tot_re[i] += acc_re[i]; tot_im[i] += acc_im[i]; }
     if (!valid) return;
     double2 *out = partial + (int64_t)blockIdx.y * N + d * (int64_t)(P * 2 * kNH);
 #pragma unroll
@@ -394,15 +397,15 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
                     } else {
                         auto &L = b32[0];
                         consume32<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx_tab[k], w0 + g * PG,
-                                      &fre[lane * NS], &fim[lane * NS]);
+                                      &are[lane * NS], &aim[lane * NS]);
                     }
                 }
             }
             if (++nb == kTileBatches) {
                 nb = 0;
                 for (int i = 0; i < 64 * NS; ++i) {
-                    tre[i] += F64 ? are[i] : (double)fre[i];
-                    tim[i] += F64 ? aim[i] : (double)fim[i];
+                    tre[i] += are[i];
+                    tim[i] += aim[i];
                     are[i] = aim[i] = 0.0;
                     fre[i] = fim[i] = 0.0f;
                 }
@@ -413,8 +416,8 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
             for (int pl = 0; pl < PG; ++pl)
                 for (int sg = 0; sg < 2; ++sg) {
                     const int i = lane * NS + 2 * pl + sg;
-                    const double re = tre[i] + (F64 ? are[i] : (double)fre[i]);
-                    const double im = tim[i] + (F64 ? aim[i] : (double)fim[i]);
+                    const double re = tre[i] + are[i];
+                    const double im = tim[i] + aim[i];
                     const int p = w0 + g * PG + pl;
                     const double m = (double)(2 * p + 1) * h;
                     const double r = sg == 0 ? m + hx_tab[k] : m - hx_tab[k];
