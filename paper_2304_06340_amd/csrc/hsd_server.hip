@@ -96,7 +96,7 @@ struct DeviceExecutor : Executor {
         for (auto &s : sl) {
             (void)hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
             (void)hipEventCreateWithFlags(&s.ev_begin, hipEventDefault);
-            (void)hipEventCreateWithFlags(&s.ev_done, hipEventDisableTiming);
+            (void)hipEventCreateWithFlags(&s.ev_done, hipEventDefault);   // timed against ev_begin
             (void)hipHostMalloc((void **)&s.host_result, 64, hipHostMallocDefault);
         }
     }
@@ -245,9 +245,9 @@ struct DeviceExecutor : Executor {
     {
         DeviceSlot &d = sl[s];
         float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, d.ev_begin, d.ev_done);
+        HSD_HIP_TRY(hipEventElapsedTime(&ms, d.ev_begin, d.ev_done));
         j.result.d2 = d.host_result[0];
-        j.result.device_ms = 0.0;
+        j.result.device_ms = (double)ms;
         if (j.params.method != HSD_METHOD_NUFFT3)
             j.result.pairs = (double)(d.mu->nt + (d.nu ? d.nu->nt : 0)) * (double)j.rule->n_nodes;
         j.result.rel_err_stated = stated_rel_err(&j.params, d.mu->nt);
