@@ -40,11 +40,6 @@ namespace hsd {
 
 constexpr int kTile = 32;          // triangles per blocked-summation tile
 constexpr double kGapFloor = 1e-150;
-// The mixed form evaluates the closed branch in FP32, whose cancellation
-// error is about eps32 / G relative to J; below G = kMixedTau it sums the
-// series in FP32 instead (no cancellation: absolute error ~eps32; terms
-// beyond n = 9 are below 3e-11 at G = 0.5).
-constexpr double kMixedTau = 0.05;
 // Gap floor of the mixed form: keeps 2J/(gap G) finite in FP32 (an exactly
 // zero gap becomes 1e-18, changing mu_T by ~1e-18 relative).
 constexpr double kGapFloor32 = 1e-18;
@@ -183,8 +178,8 @@ HSD_HD void sp_lane_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t 
             const double bc = fmax(hi - mid, kGapFloor32);
             const double tmid = t0 + mid;
             const double iG = rcp64(ac + bc);
-            const float Ka = (float)(2.0 * J * rcp64(ac) * iG);
-            const float Kb = (float)(2.0 * J * rcp64(bc) * iG);
+            const float Ka = (float)(2.0 * rcp64(ac) * iG);   // without J: applied in FP64
+            const float Kb = (float)(2.0 * rcp64(bc) * iG);
             const double r_thr = fmax(tau, kMixedTau) * iG;
             const float acf = (float)ac, bcf = (float)bc;
             const double fr[3] = {tmid, 0.5 * ac, 0.5 * bc};
@@ -211,26 +206,27 @@ HSD_HD void sp_lane_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t 
                         Eu = sg == 0 ? pmul(Cp[1], Bk[1]) : pmulc(Cp[1], Bk[1]);
                         Ev = sg == 0 ? pmul(Cp[2], Bk[2]) : pmulc(Cp[2], Bk[2]);
                     }
-                    float Yr, Xr;
+                    float Yr, Xr, half = 0.0f;
+                    double scale = J;
                     const float r = rr[slot];
                     if ((double)r < r_thr) {
-                        float fre, fim;
-                        dd2_series(r * acf, r * bcf, fre, fim);
-                        // r^2 J formed in FP64 and rounded once: an FP32 r^2
-                        // would bias every term of the node the same way
+                        dd2_series_dev(r * acf, r * bcf, Yr, Xr);
+                        // r^2 J stays in FP64: rounded to FP32 it would give
+                        // every triangle of equal area the same relative error
                         const double m = (double)(2 * (p0 + pl) + 1) * h;
                         const double rd = sg == 0 ? m + hx : m - hx;
-                        const float r2J = (float)(rd * rd * J);
-                        Yr = r2J * fre;
-                        Xr = r2J * fim;
+                        half = 0.5f;
+                        scale = rd * rd * J;
                     } else {
                         const float Pv = Kb * Ev.s;
                         const float Pu = Ka * Eu.s;
                         Yr = __builtin_fmaf(Pv, Ev.s, Pu * Eu.s);
                         Xr = __builtin_fmaf(Pv, Ev.c, -Pu * Eu.c);
                     }
-                    acc_re[slot] += (double)__builtin_fmaf(E1.c, Yr, E1.s * Xr);
-                    acc_im[slot] += (double)__builtin_fmaf(E1.c, Xr, -E1.s * Yr);
+                    const float tre = __builtin_fmaf(half, E1.c, __builtin_fmaf(E1.c, Yr, E1.s * Xr));
+                    const float tim = __builtin_fmaf(-half, E1.s, __builtin_fmaf(E1.c, Xr, -E1.s * Yr));
+                    acc_re[slot] = __builtin_fma(scale, (double)tre, acc_re[slot]);
+                    acc_im[slot] = __builtin_fma(scale, (double)tim, acc_im[slot]);
                 }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) Cp[c] = pmul(Cp[c], S[c]);
@@ -305,25 +301,25 @@ HSD_HD void gen_node_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t
             sort3(0.0, d1, d2, lo, mid, hi);
             const double a = mid - lo, b = hi - mid;
             const cs32 E1 = sincos32_acc(t0 + mid);
-            float Yr, Xr;
+            float Yr, Xr, half = 0.0f;
             if (a + b < fmax(tau, kMixedTau)) {
-                float fre, fim;
-                dd2_series((float)a, (float)b, fre, fim);
-                Yr = (float)J * fre;
-                Xr = (float)J * fim;
+                dd2_series_dev((float)a, (float)b, Yr, Xr);
+                half = 0.5f;
             } else {
                 const double ac = fmax(a, kGapFloor32), bc = fmax(b, kGapFloor32);
                 const double iG = rcp64(ac + bc);
-                const float Ka = (float)(2.0 * J * rcp64(ac) * iG);
-                const float Kb = (float)(2.0 * J * rcp64(bc) * iG);
+                const float Ka = (float)(2.0 * rcp64(ac) * iG);
+                const float Kb = (float)(2.0 * rcp64(bc) * iG);
                 const cs32 Eu = sincos32_acc(0.5 * ac);
                 const cs32 Ev = sincos32_acc(0.5 * bc);
                 const float Pv = Kb * Ev.s, Pu = Ka * Eu.s;
                 Yr = __builtin_fmaf(Pv, Ev.s, Pu * Eu.s);
                 Xr = __builtin_fmaf(Pv, Ev.c, -Pu * Eu.c);
             }
-            acc_re += (double)__builtin_fmaf(E1.c, Yr, E1.s * Xr);
-            acc_im += (double)__builtin_fmaf(E1.c, Xr, -E1.s * Yr);
+            const float tre = __builtin_fmaf(half, E1.c, __builtin_fmaf(E1.c, Yr, E1.s * Xr));
+            const float tim = __builtin_fmaf(-half, E1.s, __builtin_fmaf(E1.c, Xr, -E1.s * Yr));
+            acc_re = __builtin_fma(J, (double)tre, acc_re);   // J applied in FP64
+            acc_im = __builtin_fma(J, (double)tim, acc_im);
         }
         tot_re += acc_re;
         tot_im += acc_im;

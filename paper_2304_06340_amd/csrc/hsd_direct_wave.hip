@@ -38,10 +38,12 @@ constexpr int kNH = 8;        // node pairs per panel (16 GL nodes)
 constexpr int kTileBatches = 4;   // batches per FP64 tile sum (32 triangles)
 constexpr double kGapFloor = 1e-150;
 constexpr double kGapFloor32 = 1e-18;
-constexpr double kMixedTau = 0.05;
 
-struct Scal64 { double Ka, Kb, rthr, ac, bc, J, pad0, pad1; };
-struct Scal32 { double rthr, J; float Ka, Kb, ac, bc; };
+// Per-(triangle, direction) constants in LDS.  ce/co are the coefficients of
+// the divided-difference power series as a polynomial in the radius r:
+// Re = sum_m ce[m] r^(2m), Im = r sum_m co[m] r^(2m) (see series_coefs).
+struct Scal64 { double Ka, Kb, rthr, pad; double ce[5], co[5]; };   // ce, co carry the factor J
+struct Scal32 { double rthr, J; float Ka, Kb; float ce[5], co[5]; }; // Ka, Kb, ce, co without J
 
 template <int PG> struct Batch64 {
     Scal64 sc[kTB];
@@ -78,6 +80,40 @@ HSD_HD TriDir tri_dir(const TriRec &T, double J, double nx, double ny, double nz
     return r;
 }
 
+// Coefficients of the second divided difference of exp at (i a, 0, -i b) as
+// a power series in r for a = r ac, b = r bc:  sum_n (-i)^n r^n h_n with
+// h_n = H_n(ac, bc) / (n+2)!, H_n = sum_{m<=n} (-ac)^m bc^(n-m) (complete
+// homogeneous polynomial, by the recurrence H_n = bc H_{n-1} + (-ac)^n).
+// Split by parity: ce[m] = (-1)^m h_{2m}, co[m] = (-1)^(m+1) h_{2m+1}.
+// Through n = 9: the first omitted term is below 11 G^10 / 12! relative to
+// the leading 1/2, with G = r (ac + bc) the scaled phase spread.
+HSD_HD void series_coefs(double ac, double bc, double scale, double ce[5], double co[5])
+{
+    double H = 1.0, pw = 1.0;
+    ce[0] = 0.5 * scale;
+#pragma unroll
+    for (int n = 1; n <= 9; ++n) {
+        pw *= -ac;
+        H = __builtin_fma(H, bc, pw);
+        const double hn = H * inv_factorial(n + 2) * scale;
+        if (n & 1) co[n >> 1] = ((n >> 1) & 1) ? hn : -hn;
+        else ce[n >> 1] = ((n >> 1) & 1) ? -hn : hn;
+    }
+}
+
+// Even/odd polynomial of the series at r (r2 = r^2): returns Re, Im / r.
+template <typename T>
+HSD_HD void series_eval(const T ce[5], const T co[5], T r2, T &pe, T &po)
+{
+    pe = ce[4];
+    po = co[4];
+#pragma unroll
+    for (int m = 3; m >= 0; --m) {
+        pe = pe * r2 + ce[m];
+        po = po * r2 + co[m];
+    }
+}
+
 // Producer, FP64: part j of a triangle's batch entry.
 template <int PG>
 HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
@@ -97,9 +133,8 @@ HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, i
         sc->Ka = 2.0 * td.J * rcp64(td.ac) * td.iG;
         sc->Kb = 2.0 * td.J * rcp64(td.bc) * td.iG;
         sc->rthr = tau * td.iG;
-        sc->ac = td.ac;
-        sc->bc = td.bc;
-        sc->J = td.J;
+        sc->pad = 0.0;
+        series_coefs(td.ac, td.bc, td.J, sc->ce, sc->co);
     }
 }
 
@@ -117,7 +152,9 @@ HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 P0[3], cons
             const int slot = 2 * pl + sg;
             const double r = sg == 0 ? m + hx : m - hx;
             cs64 E[3];
-            const bool direct = (sg == 1) && (p == 0);
+            // the small-radius node h - h x_k exists only in panel 0, which a
+            // lane can hold only as its first panel
+            const bool direct = (sg == 1) && (pl == 0) && (pfirst == 0);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const cs64 prod = sg == 0 ? pmul(Cp[pl][c], Bk[c]) : pmulc(Cp[pl][c], Bk[c]);
@@ -128,14 +165,14 @@ HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 P0[3], cons
             double Yr = __builtin_fma(Pv, E[2].s, Pu * E[1].s);
             double Xr = __builtin_fma(Pv, E[2].c, -Pu * E[1].c);
             if (r < sc.rthr) {
-                double fre, fim;
-                dd2_series(r * sc.ac, r * sc.bc, fre, fim);
-                const double r2J = r * r * sc.J;
-                Yr = r2J * fre;
-                Xr = r2J * fim;
+                const double r2 = r * r;
+                double pe, po;
+                series_eval(sc.ce, sc.co, r2, pe, po);
+                Yr = r2 * pe;
+                Xr = r2 * r * po;
             }
-            acc_re[slot] += __builtin_fma(E[0].c, Yr, E[0].s * Xr);
-            acc_im[slot] += __builtin_fma(E[0].c, Xr, -E[0].s * Yr);
+            acc_re[slot] = __builtin_fma(E[0].c, Yr, __builtin_fma(E[0].s, Xr, acc_re[slot]));
+            acc_im[slot] = __builtin_fma(E[0].c, Xr, __builtin_fma(-E[0].s, Yr, acc_im[slot]));
         }
     }
 }
@@ -156,18 +193,25 @@ HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, i
         for (int q = 0; q < PG; ++q) Cp[q][c] = sincos32_acc((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c]);
     }
     if (sc) {
-        sc->Ka = (float)(2.0 * td.J * rcp64(td.ac) * td.iG);
-        sc->Kb = (float)(2.0 * td.J * rcp64(td.bc) * td.iG);
+        sc->Ka = (float)(2.0 * rcp64(td.ac) * td.iG);
+        sc->Kb = (float)(2.0 * rcp64(td.bc) * td.iG);
         sc->rthr = fmax(tau, kMixedTau) * td.iG;
-        sc->ac = (float)td.ac;
-        sc->bc = (float)td.bc;
         sc->J = td.J;
+        double ce[5], co[5];
+        series_coefs(td.ac, td.bc, 1.0, ce, co);
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            sc->ce[m] = (float)ce[m];
+            sc->co[m] = (float)co[m];
+        }
     }
 }
 
-// Consumer, mixed: FP32 node arithmetic; each contribution is added in FP64
-// (an FP32 tile sum of the nearly coherent terms at small |xi| would lose
-// ~sqrt(tile) eps32 of the whole transform).
+// Consumer, mixed: FP32 node arithmetic on J-free quantities; the factor J
+// (closed branch) or r^2 J (series) is applied in FP64 as each contribution
+// is added to its FP64 running sum.  Rounding J or r^2 to FP32 would give
+// every triangle of equal area (most of a symmetric mesh) the same relative
+// error, which does not average out over the triangles.
 template <int PG>
 HSD_HD void consume32(const Scal32 &sc, const cs32 Bk[3], const cs32 P0[3], const cs32 (*Cp)[3], double h,
                       double hx, int pfirst, double *acc_re, double *acc_im)
@@ -180,29 +224,41 @@ HSD_HD void consume32(const Scal32 &sc, const cs32 Bk[3], const cs32 P0[3], cons
         for (int sg = 0; sg < 2; ++sg) {
             const int slot = 2 * pl + sg;
             const double rd = sg == 0 ? m + hx : m - hx;
-            const float r = (float)rd;
             cs32 E[3];
-            const bool direct = (sg == 1) && (p == 0);
+            const bool direct = (sg == 1) && (pl == 0) && (pfirst == 0);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const cs32 prod = sg == 0 ? pmul(Cp[pl][c], Bk[c]) : pmulc(Cp[pl][c], Bk[c]);
                 E[c] = direct ? P0[c] : prod;
             }
-            float Yr, Xr;
+            const float Pv = sc.Kb * E[2].s;
+            const float Pu = sc.Ka * E[1].s;
+            float Yr = __builtin_fmaf(Pv, E[2].s, Pu * E[1].s);
+            float Xr = __builtin_fmaf(Pv, E[2].c, -Pu * E[1].c);
+            double scale = sc.J;
+            float half = 0.0f;
             if (rd < sc.rthr) {
-                float fre, fim;
-                dd2_series(r * sc.ac, r * sc.bc, fre, fim);
-                const float r2J = (float)(rd * rd * sc.J);
-                Yr = r2J * fre;
-                Xr = r2J * fim;
-            } else {
-                const float Pv = sc.Kb * E[2].s;
-                const float Pu = sc.Ka * E[1].s;
-                Yr = __builtin_fmaf(Pv, E[2].s, Pu * E[1].s);
-                Xr = __builtin_fmaf(Pv, E[2].c, -Pu * E[1].c);
+                // Re of the series minus its constant 1/2; the 1/2 term is
+                // added last, in one fused step with the rest of the product
+                // already summed, so that the rounding sees the exact total
+                // (1/2 rounded first and a sub-ulp rest added after it would
+                // err the same way for every triangle of a node).
+                const double r2d = rd * rd;
+                const float r2 = (float)r2d;
+                float pe = sc.ce[4], po = sc.co[4];
+#pragma unroll
+                for (int q = 3; q >= 1; --q) pe = __builtin_fmaf(pe, r2, sc.ce[q]);
+#pragma unroll
+                for (int q = 3; q >= 0; --q) po = __builtin_fmaf(po, r2, sc.co[q]);
+                Yr = pe * r2;
+                Xr = (float)rd * po;
+                half = 0.5f;
+                scale = r2d * sc.J;
             }
-            acc_re[slot] += (double)__builtin_fmaf(E[0].c, Yr, E[0].s * Xr);
-            acc_im[slot] += (double)__builtin_fmaf(E[0].c, Xr, -E[0].s * Yr);
+            const float tre = __builtin_fmaf(half, E[0].c, __builtin_fmaf(E[0].c, Yr, E[0].s * Xr));
+            const float tim = __builtin_fmaf(-half, E[0].s, __builtin_fmaf(E[0].c, Xr, -E[0].s * Yr));
+            acc_re[slot] = __builtin_fma(scale, (double)tre, acc_re[slot]);
+            acc_im[slot] = __builtin_fma(scale, (double)tim, acc_im[slot]);
         }
     }
 }

@@ -16,6 +16,13 @@
 
 namespace hsd {
 
+// The mixed form evaluates the closed branch of the triangle transform in
+// FP32, where the difference sinc b - sinc a cancels: the error is about
+// 2 eps32 / G relative to the triangle's term at phase spread G.  Below
+// G = kMixedTau it sums the power series instead (no cancellation; terms past
+// the ninth power are below 1e-13 relative at G = 0.25).
+constexpr double kMixedTau = 0.25;
+
 // One triangle as the affine image p0 + [e1 e2] u of the standard simplex
 // (eq. def_affine_simplex) with its area ratio J = |e1 x e2| (gamma in eq.
 // simplex32_ft).  80 bytes, read by whole wavefronts at once (scalar loads).

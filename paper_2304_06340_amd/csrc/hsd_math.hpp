@@ -202,12 +202,26 @@ HSD_HD void sort3(T x0, T x1, T x2, T &lo, T &mid, T &hi)
 // summed through n = 9; the first omitted term is below 11 G^10 / 12! with
 // G = a + b (4e-27 at G = 0.01, 2e-11 at G = 0.5).
 template <typename T>
+HSD_HD void dd2_series_dev(T a, T b, T &re, T &im);
+
+template <typename T>
 HSD_HD void dd2_series(T a, T b, T &re, T &im)
+{
+    dd2_series_dev(a, b, re, im);
+    re += (T)0.5;
+}
+
+// The same series without its constant term 1/2 (re is Re - 1/2).  The
+// mixed form adds the 1/2 term last, fused with the already summed rest: at
+// the smallest radii the rest is below one FP32 ulp of 1/2, and adding it to
+// a rounded 1/2-term would err the same way for every triangle of a node.
+template <typename T>
+HSD_HD void dd2_series_dev(T a, T b, T &re, T &im)
 {
     const T na = -a;
     T pw = na;
     T H = b + na;                       // H_1
-    T sre = (T)0.5;                     // n = 0
+    T sre = (T)0.0;                     // n = 0 term (1/2) left out
     T sim = -H * (T)inv_factorial(3);   // n = 1
     pw *= na; H = H * b + pw; sre -= H * (T)inv_factorial(4);   // n = 2
     pw *= na; H = H * b + pw; sim += H * (T)inv_factorial(5);   // n = 3
