@@ -107,13 +107,22 @@ typedef struct {
     double s;            /* Sobolev order: weight (1+|xi|^2)^-s; finite, s >= 0   */
     int32_t form;        /* HSD_FORM_*                                             */
     int32_t method;      /* HSD_METHOD_*                                           */
-    double taylor_tau;   /* series branch when the largest phase gap < tau (1e-2)  */
+    double taylor_tau;   /* series branch when the phase spread G < tau (1e-2);
+                            FP64: (0, 0.05]; mixed: (0, 0.25], and the mixed
+                            form uses max(tau, 0.1)                            */
     int32_t tri_rule;    /* HSD_TRI_* (NUFFT3 only)                                */
     double nufft_tol;    /* requested NUFFT accuracy (sets the width if width==0)  */
     int32_t nufft_width; /* ES kernel width in grid points (0: from tol)           */
     double nufft_sigma;  /* oversampling factor (2.0)                              */
     int32_t k_splits;    /* triangle splits of the direct sum (0: automatic)       */
-    int32_t reserved[7];
+    int32_t reserved0;
+    double freq_unit;    /* kappa in the weight (1+(|xi|/kappa)^2)^-s; 1 (or 0):
+                            the library's exp(-i xi.x) convention; 2 pi: the
+                            paper's exp(-2 pi i eta.x) convention (section 2.1)
+                            with nodes xi = 2 pi eta, which makes d2 the paper's
+                            H_{-s} norm of eq. sobolev_2 (s >= 0 here is the
+                            paper's -s)                                          */
+    int32_t reserved[4];
 } hsd_params;
 
 typedef struct {

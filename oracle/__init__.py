@@ -189,9 +189,15 @@ def nu_hat_sphere(r):
     return out
 
 
-def sobolev_weights(rule: Rule, s: float) -> np.ndarray:
-    """W_k = (2 pi)^-3 w_k (1 + |xi_k|^2)^-s."""
-    return rule.weights * (1.0 + rule.radii ** 2) ** (-s) / (2.0 * math.pi) ** 3
+def sobolev_weights(rule: Rule, s: float, freq_unit: float = 1.0) -> np.ndarray:
+    """W_k = (2 pi)^-3 w_k (1 + (|xi_k|/kappa)^2)^-s, kappa = freq_unit.
+
+    kappa = 1 is the exp(-i xi.x) convention.  kappa = 2 pi with nodes
+    xi = 2 pi eta is the paper's exp(-2 pi i eta.x) convention of section 2.1:
+    there the transform at xi equals the paper's at eta, and (2 pi)^-3 w_k is
+    the paper's quadrature weight in eta, so d^2 becomes eq. sobolev_2 with
+    the paper's order -s."""
+    return rule.weights * (1.0 + (rule.radii / freq_unit) ** 2) ** (-s) / (2.0 * math.pi) ** 3
 
 
 # --------------------------------------------------------------------------
@@ -246,11 +252,11 @@ def residual(verts, tris, rule: Rule, verts2=None, tris2=None, tau: float = TAU_
 
 
 def distance(verts, tris, rule: Rule, s: float = 1.0, verts2=None, tris2=None,
-             tau: float = TAU_DEFAULT, return_residual: bool = False):
+             tau: float = TAU_DEFAULT, return_residual: bool = False, freq_unit: float = 1.0):
     """d^2 = sum_k W_k |R_k|^2 (eq. sobolev_2 on the quadrature), summed with
     math.fsum in node order."""
     R = residual(verts, tris, rule, verts2, tris2, tau)
-    W = sobolev_weights(rule, s)
+    W = sobolev_weights(rule, s, freq_unit)
     d2 = math.fsum((W * (R.real ** 2 + R.imag ** 2)).tolist())
     return (d2, R) if return_residual else d2
 

@@ -33,7 +33,7 @@ class Params(C.Structure):
     _fields_ = [("s", C.c_double), ("form", C.c_int32), ("method", C.c_int32),
                 ("taylor_tau", C.c_double), ("tri_rule", C.c_int32), ("nufft_tol", C.c_double),
                 ("nufft_width", C.c_int32), ("nufft_sigma", C.c_double), ("k_splits", C.c_int32),
-                ("reserved", C.c_int32 * 7)]
+                ("reserved0", C.c_int32), ("freq_unit", C.c_double), ("reserved", C.c_int32 * 4)]
 
 
 class Result(C.Structure):

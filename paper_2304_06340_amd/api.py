@@ -55,6 +55,9 @@ class Params:
     nufft_width: int = 0
     nufft_sigma: float = 2.0
     k_splits: int = 0
+    # kappa of the weight (1+(|xi|/kappa)^2)^-s; 2 pi gives the paper's
+    # exp(-2 pi i eta.x) convention for nodes xi = 2 pi eta (section 2.1)
+    freq_unit: float = 1.0
 
     def to_c(self) -> L.Params:
         p = L.Params()
@@ -68,6 +71,7 @@ class Params:
         p.nufft_width = int(self.nufft_width)
         p.nufft_sigma = float(self.nufft_sigma)
         p.k_splits = int(self.k_splits)
+        p.freq_unit = float(self.freq_unit)
         return p
 
 

@@ -134,8 +134,15 @@ hsd_status validate_params(const hsd_params *p)
         set_error("unknown method %d", p->method);
         return HSD_EINVAL;
     }
-    if (!(p->taylor_tau > 0.0) || p->taylor_tau > 0.05) {
-        set_error("taylor_tau must be in (0, 0.05] (got %g)", p->taylor_tau);
+    // the series is summed through the ninth power: its truncation stays
+    // below FP64 rounding for G < 0.05 and below 1e-13 for G < 0.25
+    const double tau_max = p->form == HSD_FORM_MIXED ? 0.25 : 0.05;
+    if (!(p->taylor_tau > 0.0) || p->taylor_tau > tau_max) {
+        set_error("taylor_tau must be in (0, %g] for this form (got %g)", tau_max, p->taylor_tau);
+        return HSD_EINVAL;
+    }
+    if (!std::isfinite(p->freq_unit) || p->freq_unit < 0.0) {
+        set_error("freq_unit must be finite and > 0, or 0 for 1 (got %g)", p->freq_unit);
         return HSD_EINVAL;
     }
     return HSD_OK;
@@ -157,11 +164,16 @@ double stated_rel_err(const hsd_params *p, int64_t nt)
 
 // Per-s tables of a rule: SP -> radial W_r = w_r r^2 (1+r^2)^-s (2 pi)^-3 and
 // nu_r = 4 pi sin r / r; general -> per node W and nu.
-hsd_status rule_tables(hsd_rule *rule, double s, hipStream_t st, const double **wtab,
+double freq_unit_of(const hsd_params *p) { return p->freq_unit > 0.0 ? p->freq_unit : 1.0; }
+
+hsd_status rule_tables(hsd_rule *rule, const hsd_params *p, hipStream_t st, const double **wtab,
                        const double **nutab)
 {
+    const double s = p->s, kappa = freq_unit_of(p);
+    const double ik2 = 1.0 / (kappa * kappa);
+    const std::pair<double, double> key(s, kappa);
     std::lock_guard<std::mutex> lk(rule->mu);
-    auto it = rule->tabs.find(s);
+    auto it = rule->tabs.find(key);
     if (it != rule->tabs.end()) {
         *wtab = it->second->w.as<const double>();
         *nutab = it->second->nu.as<const double>();
@@ -179,7 +191,7 @@ hsd_status rule_tables(hsd_rule *rule, double s, hipStream_t st, const double **
         nu.resize(rule->n_rad);
         for (int64_t i = 0; i < rule->n_rad; ++i) {
             const double r = sp.radii[i];
-            W[i] = sp.wr[i] * r * r * std::pow(1.0 + r * r, -s) * inv8pi3;
+            W[i] = sp.wr[i] * r * r * std::pow(1.0 + r * r * ik2, -s) * inv8pi3;
             nu[i] = nu_of(r);
         }
     } else {
@@ -187,7 +199,7 @@ hsd_status rule_tables(hsd_rule *rule, double s, hipStream_t st, const double **
         nu.resize(rule->n_nodes);
         for (int64_t i = 0; i < rule->n_nodes; ++i) {
             const double r = rule->host_radii[i];
-            W[i] = rule->host_weights[i] * std::pow(1.0 + r * r, -s) * inv8pi3;
+            W[i] = rule->host_weights[i] * std::pow(1.0 + r * r * ik2, -s) * inv8pi3;
             nu[i] = nu_of(r);
         }
     }
@@ -200,7 +212,7 @@ hsd_status rule_tables(hsd_rule *rule, double s, hipStream_t st, const double **
     HSD_HIP_TRY(hipStreamSynchronize(st));
     *wtab = t->w.as<const double>();
     *nutab = t->nu.as<const double>();
-    rule->tabs[s] = std::move(t);
+    rule->tabs[key] = std::move(t);
     return HSD_OK;
 }
 
@@ -215,7 +227,7 @@ hsd_status distance_core(hsd_ctx *ctx, hipStream_t st, const hsd_mesh *mu, const
     hsd_rule *rule = const_cast<hsd_rule *>(rule_c);
     hsd_status stt;
     const double *wtab = nullptr, *nutab = nullptr;
-    if ((stt = rule_tables(rule, p->s, st, &wtab, &nutab)) != HSD_OK) return stt;
+    if ((stt = rule_tables(rule, p, st, &wtab, &nutab)) != HSD_OK) return stt;
     const int64_t N = rule->n_nodes;
     MeshPair mp;
     mp.A = mu->tris.as<const TriRec>();
@@ -375,6 +387,7 @@ void hsd_params_default(hsd_params *p)
     p->nufft_width = 0;
     p->nufft_sigma = 2.0;
     p->k_splits = 0;
+    p->freq_unit = 1.0;
 }
 
 hsd_status hsd_init(int device, size_t budget, hsd_ctx **out)
@@ -722,7 +735,7 @@ hsd_status hsd_distance_grad(hsd_ctx *ctx, const hsd_mesh *mu, const hsd_mesh *n
                              &d_res, &pairs, ctx->evt0, ctx->evt1)) != HSD_OK)
         return stt;
     const double *wtab = nullptr, *nutab = nullptr;
-    if ((stt = rule_tables(rule, p->s, st, &wtab, &nutab)) != HSD_OK) return stt;
+    if ((stt = rule_tables(rule, p, st, &wtab, &nutab)) != HSD_OK) return stt;
     const bool sp = rule->kind == HSD_RULE_SPHERICAL_PRODUCT;
     const int64_t n_dir = sp ? rule->n_dir : rule->n_nodes;
     const int n_rad = sp ? (int)rule->n_rad : 1;

@@ -19,9 +19,10 @@ namespace hsd {
 // The mixed form evaluates the closed branch of the triangle transform in
 // FP32, where the difference sinc b - sinc a cancels: the error is about
 // 2 eps32 / G relative to the triangle's term at phase spread G.  Below
-// G = kMixedTau it sums the power series instead (no cancellation; terms past
-// the ninth power are below 1e-13 relative at G = 0.25).
-constexpr double kMixedTau = 0.25;
+// G = max(taylor_tau, kMixedTau) it sums the power series instead (no
+// cancellation; terms past the ninth power are below 1e-13 relative at
+// G = 0.25, the largest threshold accepted for this form).
+constexpr double kMixedTau = 0.1;
 
 // One triangle as the affine image p0 + [e1 e2] u of the standard simplex
 // (eq. def_affine_simplex) with its area ratio J = |e1 x e2| (gamma in eq.
@@ -147,7 +148,7 @@ struct hsd_rule {
         hsd::DevBuf w;                        // w (1+r^2)^-s (2pi)^-3 (SP: w_r r^2 ...)
         hsd::DevBuf nu;                       // sphere transform 4 pi sin r / r
     };
-    std::map<double, std::unique_ptr<Tables>> tabs;
+    std::map<std::pair<double, double>, std::unique_ptr<Tables>> tabs;   // by (s, freq_unit)
     std::mutex mu;
     std::atomic<int> refs{1};
     ~hsd_rule();
@@ -206,7 +207,8 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc,
                                 const hsd_params *p, double2 *out, double *pairs);
 
 // Shared host helpers (hsd_core.hip).
-hsd_status rule_tables(hsd_rule *rule, double s, hipStream_t st, const double **wtab,
+double freq_unit_of(const hsd_params *p);
+hsd_status rule_tables(hsd_rule *rule, const hsd_params *p, hipStream_t st, const double **wtab,
                        const double **nutab);
 hsd_status validate_params(const hsd_params *p);
 double stated_rel_err(const hsd_params *p, int64_t nt);

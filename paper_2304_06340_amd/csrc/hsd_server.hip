@@ -151,7 +151,7 @@ struct DeviceExecutor : Executor {
                                              (int64_t)j.t2.size() / 3, HSD_MEM_HOST, &d.nu)) != HSD_OK)
             return st;
         const double *w = nullptr, *nuv = nullptr;
-        if ((st = rule_tables(j.rule, j.params.s, d.stream, &w, &nuv)) != HSD_OK) return st;
+        if ((st = rule_tables(j.rule, &j.params, d.stream, &w, &nuv)) != HSD_OK) return st;
         d.K = k_of(j);
         const int64_t N = j.rule->n_nodes;
         if ((st = d.partial.ensure(ctx, (size_t)d.K * N * sizeof(double2))) != HSD_OK) return st;
@@ -223,7 +223,7 @@ struct DeviceExecutor : Executor {
         HSD_HIP_TRY(hipSetDevice(ctx->device));
         const double *w = nullptr, *nuv = nullptr;
         hsd_status st;
-        if ((st = rule_tables(j.rule, j.params.s, d.stream, &w, &nuv)) != HSD_OK) return st;
+        if ((st = rule_tables(j.rule, &j.params, d.stream, &w, &nuv)) != HSD_OK) return st;
         const int64_t N = j.rule->n_nodes;
         const int64_t nb = finalize_blocks(N);
         if ((st = d.redbuf.ensure(ctx, (size_t)(nb + 1) * sizeof(double))) != HSD_OK) return st;

@@ -228,10 +228,50 @@ def test_invalid_inputs_are_rejected(hsd_ctx):
         hsd.Mesh(hsd_ctx, bad, f)
     mesh = hsd.Mesh(hsd_ctx, v, f)
     g = hsd.Rule.spherical_product(hsd_ctx, 8.0, 2, 4, 4, 4)
-    for p in (hsd.Params(s=-1.0), hsd.Params(s=float("nan")), hsd.Params(taylor_tau=0.0)):
+    for p in (hsd.Params(s=-1.0), hsd.Params(s=float("nan")), hsd.Params(taylor_tau=0.0),
+              hsd.Params(taylor_tau=0.1), hsd.Params(form="mixed", taylor_tau=0.3),
+              hsd.Params(freq_unit=-1.0), hsd.Params(freq_unit=float("inf"))):
         with pytest.raises(hsd.HsdError):
             hsd.distance(hsd_ctx, mesh, None, g, p)
     with pytest.raises(hsd.HsdError):
         hsd.Rule.spherical_product(hsd_ctx, 8.0, 2, 5, 4, 4)   # odd nodes per panel
     with pytest.raises(hsd.HsdError):
         hsd.Rule.cube_trapezoid(hsd_ctx, 5.0, 7)
+
+
+def test_paper_convention_mode(hsd_ctx, orc):
+    """freq_unit = 2 pi with nodes xi = 2 pi eta: the paper's exp(-2 pi i eta.x)
+    convention and its H_-10 norm (section 2.1, eq. sobolev_2).  Parity with
+    the oracle at level 2 on an M = 64 trapezoid grid; the empty mesh against
+    eq. sphere_sobolev_exact on the paper's M = 128 grid; then the replay of
+    Fig. 3(b): relative errors falling by about 4 per level on that grid and
+    extrapolating to the level of 1e-5 at N = 7 (section 4.2)."""
+    exact = orc.sphere_norm_paper(-10.0)
+    p = hsd.Params(s=10.0, freq_unit=2 * math.pi)
+    xi = 2 * math.pi * 5.0
+    r64 = hsd.Rule.cube_trapezoid(hsd_ctx, xi, 64)
+    v, f = icosphere(2)
+    m = hsd.Mesh(hsd_ctx, v, f)
+    got = hsd.distance(hsd_ctx, m, None, r64, p).d2
+    ref = orc.distance(v, f, orc.cube_trapezoid_rule(xi, 64), 10.0, freq_unit=2 * math.pi)
+    print(f"paper convention level 2, M=64: gpu {got:.12e} oracle {ref:.12e}")
+    assert abs(got - ref) <= 1e-10 * ref
+    m.close()
+    r128 = hsd.Rule.cube_trapezoid(hsd_ctx, xi, 128)
+    empty = hsd.Mesh(hsd_ctx, np.zeros((0, 3)), np.zeros((0, 3), np.int32))
+    e = hsd.distance(hsd_ctx, empty, None, r128, p).d2
+    assert abs(e - exact) <= 1e-12 * exact
+    rel = []
+    for level in (3, 4, 5, 6):
+        v, f = icosphere(level)
+        m = hsd.Mesh(hsd_ctx, v, f)
+        rel.append(math.sqrt(hsd.distance(hsd_ctx, m, None, r128, p).d2 / exact))
+        m.close()
+    ratios = [a / b for a, b in zip(rel[:-1], rel[1:])]
+    print("paper convention, M=128: relative H_-10 errors levels 3-6", ["%.3e" % x for x in rel],
+          "ratios", ["%.3f" % x for x in ratios])
+    assert all(3.8 < q < 4.2 for q in ratios)
+    assert 5e-6 < rel[-1] / 4 < 5e-5
+    empty.close()
+    r64.close()
+    r128.close()

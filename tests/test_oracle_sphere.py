@@ -136,3 +136,40 @@ def test_quadratic_convergence_of_icosahedral_meshes(orc):
     ratios = [d[i] / d[i + 1] for i in range(len(d) - 1)]
     assert 3.0 < ratios[0] < 4.5
     assert 3.7 < ratios[1] < 4.3 and 3.85 < ratios[2] < 4.15, ratios
+
+
+def test_paper_convention_trapezoid_reaches_closed_form(orc):
+    """Paper convention (section 2.1: exp(-2 pi i eta.x), order -10): the
+    empty-mesh distance is the sphere's own H_-10 norm, which the trapezoid
+    rule on [-5, 5]^3 (eq. trap_rule_R3) approximates to about 1e-13 at
+    M = 128 (section 4.1, Fig. 1(b)); eq. sphere_sobolev_exact gives it in
+    closed form.  Nodes are xi = 2 pi eta and freq_unit = 2 pi."""
+    exact = orc.sphere_norm_paper(-10.0)
+    rule = orc.cube_trapezoid_rule(2 * math.pi * 5.0, 128)
+    W = orc.sobolev_weights(rule, 10.0, 2 * math.pi)
+    nu = orc.nu_hat_sphere(rule.radii)
+    got = math.fsum((W * nu * nu).tolist())
+    assert abs(got - exact) <= 1e-12 * exact
+    # the same norm from a radial product rule on |eta| <= 5 (tail below 1e-14)
+    sp = orc.spherical_product_rule(2 * math.pi * 5.0, 8, 16, 4, 4)
+    W = orc.sobolev_weights(sp, 10.0, 2 * math.pi)
+    nu = orc.nu_hat_sphere(sp.radii)
+    assert abs(math.fsum((W * nu * nu).tolist()) - exact) <= 1e-12 * exact
+
+
+def test_paper_convention_quadratic_convergence(orc):
+    """Section 4.2, Fig. 3(b): relative H_-10 errors ||T_N - S^2|| / ||S^2||
+    fall by about 4 per subdivision and reach the level of 1e-5 at N = 7
+    (trapezoid rule, xi_max = 5).  Levels 0-2 on an M = 64 grid (whose own
+    error is 1.4e-7 relative, far below these) must show the ratio rising
+    towards 4, and extrapolating by 4^-5 from N = 2 must land at that level."""
+    from hsd_inputs import icosphere
+    exact = orc.sphere_norm_paper(-10.0)
+    rule = orc.cube_trapezoid_rule(2 * math.pi * 5.0, 64)
+    rel = []
+    for level in (0, 1, 2):
+        v, f = icosphere(level)
+        rel.append(math.sqrt(orc.distance(v, f, rule, 10.0, freq_unit=2 * math.pi) / exact))
+    r01, r12 = rel[0] / rel[1], rel[1] / rel[2]
+    assert 3.0 < r01 < r12 < 4.2
+    assert 5e-6 < rel[2] / 4 ** 5 < 5e-5
