@@ -42,6 +42,13 @@ WORKLOADS = {
 }
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (256 CU x 2.4 GHz x 128 FLOP/clk)
+
+# HBM bytes per launch of k_direct_wave<2,FP64> measured with rocprofv3 for the
+# current kernel revision: FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the factors
+# read off a 1 GiB device copy in the same runs
+# (profiles/k_direct_wave_fp64_level7_large_rule.md).  Re-measure after any
+# change to the kernel; other workloads were not measured.
+MEASURED_TRAFFIC = {"level7-large-rule": (3243892.5625 * 2.0 + 131072.0) * 1024.0}
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (256 CU x 2.4 GHz x 256 FLOP/clk)
 
 
@@ -146,7 +153,10 @@ def main():
     flop_pair = flops_per_pair(spec)
     achieved = flop_pair * pairs / (kern_ms * 1e-3) / 1e12
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                       "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                       "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                       "traffic": MEASURED_TRAFFIC.get(args.workload),
+                       "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, "
+                                       "scaled by a plain copy's counters",
                        "kernel": "k_direct_wave<FP64>", "kernel_ms": kern_ms,
                        "flops_per_pair": flop_pair}
     if not args.no_mixed:

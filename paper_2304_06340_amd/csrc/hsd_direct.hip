@@ -747,4 +747,24 @@ void hsd__host_sincos64(const double *x, int64_t n, double *c, double *s)
     }
 }
 
+void hsd__host_sincos64_tab(const double *x, int64_t n, double *c, double *s)
+{
+    hsd::cs64 turn[32];
+    for (int k = 0; k < 32; ++k) turn[k] = hsd::turn16(k);
+    for (int64_t i = 0; i < n; ++i) {
+        const hsd::cs64 r = hsd::sincos64_tab(x[i], turn);
+        c[i] = r.c;
+        s[i] = r.s;
+    }
+}
+
+void hsd__host_sincos32(const double *x, int64_t n, float *c, float *s)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const hsd::cs32 r = hsd::sincos32_acc(x[i]);
+        c[i] = r.c;
+        s[i] = r.s;
+    }
+}
+
 } // extern "C"

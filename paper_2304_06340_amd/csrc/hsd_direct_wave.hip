@@ -117,17 +117,17 @@ HSD_HD void series_eval(const T ce[5], const T co[5], T r2, T &pe, T &po)
 // Producer, FP64: part j of a triangle's batch entry.
 template <int PG>
 HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
-                      Scal64 *sc, cs64 Bk[3], cs64 P0[3], cs64 Cp[PG][3])
+                      const cs64 *turn, Scal64 *sc, cs64 Bk[3], cs64 P0[3], cs64 Cp[PG][3])
 {
     const double fr[3] = {td.tmid, 0.5 * td.ac, 0.5 * td.bc};
     const double hx = hx_tab[j];
     const double r0 = h - hx;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        Bk[c] = sincos64(hx * fr[c]);
-        P0[c] = sincos64(r0 * fr[c]);
+        Bk[c] = sincos64_tab(hx * fr[c], turn);
+        P0[c] = sincos64_tab(r0 * fr[c], turn);
 #pragma unroll
-        for (int q = 0; q < PG; ++q) Cp[q][c] = sincos64((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c]);
+        for (int q = 0; q < PG; ++q) Cp[q][c] = sincos64_tab((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c], turn);
     }
     if (sc) {
         sc->Ka = 2.0 * td.J * rcp64(td.ac) * td.iG;
@@ -286,7 +286,12 @@ __global__ __launch_bounds__(256) void k_direct_wave(
     constexpr int NS = 2 * PG;
     constexpr bool F64 = FORM == HSD_FORM_FP64;
     __shared__ typename std::conditional<F64, Batch64<PG>, Batch32<PG>>::type lds[4];
+    __shared__ cs64 turn[F64 ? 32 : 1];     // e^{i k pi/16} for the FP64 sin/cos
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if constexpr (F64) {
+        if (threadIdx.x < 32) turn[threadIdx.x] = turn16((int)threadIdx.x);
+        __syncthreads();
+    }
     const int wpd = P / (kNH * PG);                 // waves per direction
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
     const bool valid = gw < d_count * wpd;
@@ -319,7 +324,7 @@ __global__ __launch_bounds__(256) void k_direct_wave(
             const TriRec *rp = wv::tri_at(A, nA, B, gi, J);
             const TriDir td = tri_dir(*rp, J, nx, ny, nz, F64 ? kGapFloor : kGapFloor32);
             if constexpr (F64)
-                produce64<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
+                produce64<PG>(td, h, hx_tab, pj, w0, tau, turn, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
                               L.P0[pt][pj], &L.Cp[pt][pj * PG]);
             else
                 produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
@@ -420,6 +425,8 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
     const int wpd = P / (kNH * PG);
     std::vector<Batch64<PG>> b64(1);
     std::vector<Batch32<PG>> b32(1);
+    cs64 turn[32];
+    for (int k = 0; k < 32; ++k) turn[k] = turn16(k);
     for (int wi = 0; wi < wpd; ++wi) {
         const int w0 = wi * kNH * PG;
         std::vector<double> tre(64 * NS, 0.0), tim(64 * NS, 0.0);
@@ -435,7 +442,7 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
                 const TriDir td = tri_dir(*rp, J, nx, ny, nz, F64 ? kGapFloor : kGapFloor32);
                 if (F64) {
                     auto &L = b64[0];
-                    produce64<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
+                    produce64<PG>(td, h, hx_tab, pj, w0, tau, turn, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
                                   L.P0[pt][pj], &L.Cp[pt][pj * PG]);
                 } else {
                     auto &L = b32[0];

@@ -80,6 +80,48 @@ HSD_HD cs64 sincos64(double x)
     return cs64{c, s};
 }
 
+// e^{i k pi/16} for k = 0..31 as (cos, sin): the eighth-quadrant values
+// k = 0..7 from sincos64, the others by exact quarter-turn rotations, so that
+// multiples of pi/2 give exact 0 and +-1.
+HSD_HD cs64 turn16(int k)
+{
+    const int j = k & 7, quad = (k >> 3) & 3;
+    const cs64 b = j == 0 ? cs64{1.0, 0.0} : sincos64((double)j * (kPio2Hi / 8.0));
+    switch (quad) {
+    case 0: return b;
+    case 1: return cs64{-b.s, b.c};
+    case 2: return cs64{-b.c, -b.s};
+    default: return cs64{b.s, -b.c};
+    }
+}
+
+// (cos x, sin x) with x reduced by pi/16 instead of pi/2: x = q pi/16 + r,
+// |r| <= pi/32, then e^{ix} = T[q mod 32] e^{ir} with T = turn16 (tab holds
+// its 32 entries).  The short interval needs sin r through r^9 and cos r
+// through r^8 (first omitted terms below 3e-19 and 2.2e-17); one complex
+// product replaces the quadrant logic.  For q = 0 the result is the
+// polynomial itself, so small angles keep full relative accuracy.
+HSD_HD cs64 sincos64_tab(double x, const cs64 *tab)
+{
+    constexpr double kPi16Hi = kPio2Hi / 8.0, kPi16Lo = kPio2Lo / 8.0;   // exact scalings
+    const double q = __builtin_rint(x * (8.0 * kTwoOverPi));
+    double r = __builtin_fma(-q, kPi16Hi, x);
+    r = __builtin_fma(-q, kPi16Lo, r);
+    const double r2 = r * r;
+    double ps = inv_factorial(9);
+    ps = __builtin_fma(ps, r2, -inv_factorial(7));
+    ps = __builtin_fma(ps, r2, inv_factorial(5));
+    ps = __builtin_fma(ps, r2, -inv_factorial(3));
+    const double sn = __builtin_fma(ps * r2, r, r);
+    double pc = inv_factorial(8);
+    pc = __builtin_fma(pc, r2, -inv_factorial(6));
+    pc = __builtin_fma(pc, r2, inv_factorial(4));
+    pc = __builtin_fma(pc, r2, -0.5);
+    const double cn = __builtin_fma(pc, r2, 1.0);
+    const cs64 t = tab[(int)q & 31];
+    return cs64{__builtin_fma(t.c, cn, -t.s * sn), __builtin_fma(t.s, cn, t.c * sn)};
+}
+
 // FP32 sin/cos of an angle x given in FP64, accurate to ~1 ulp of FP32 in
 // the relative sense also near zero (the hardware unit is not: it carries an
 // absolute error near 1e-7, i.e. ~1e-6 relative for small angles, which the
