@@ -83,7 +83,7 @@ def main():
     ap.add_argument("--workload", default="level7-large-rule", choices=sorted(WORKLOADS))
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-nodes", type=int, default=2048)
+    ap.add_argument("--cpu-nodes", type=int, default=10240)
     ap.add_argument("--no-nufft", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
