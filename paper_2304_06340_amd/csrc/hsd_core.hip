@@ -618,6 +618,8 @@ hsd_status hsd_freq_rule(hsd_ctx *ctx, const hsd_rule_desc *d, hsd_rule **out)
             const int M = d->M;
             const double h = 2.0 * d->xi_max / M;
             const int64_t m1 = M + 1;
+            r->cube_M = M;
+            r->cube_h = h;
             r->n_nodes = m1 * m1 * m1;
             r->host_nodes.resize((size_t)r->n_nodes * 3);
             r->host_weights.resize((size_t)r->n_nodes);

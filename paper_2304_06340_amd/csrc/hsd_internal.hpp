@@ -73,7 +73,7 @@ struct Scratch {
 // or by a serving slot).
 struct FftPlan;
 struct NufftScratch {
-    DevBuf pts, spts, keys, counts, offs, cursor, perm, grid1, fine, tri, ftq, hinv;
+    DevBuf pts, spts, keys, keys2, iota, counts, offs, perm, sorttmp, grid1, fine, tri, ftq, hinv;
     std::unique_ptr<FftPlan> plan;
     NufftScratch();
     ~NufftScratch();
@@ -142,6 +142,8 @@ struct hsd_rule {
     hsd::DevBuf d_hx;                         // SP: h*x for the positive half [n/2]
     hsd::DevBuf d_radii;                      // SP: radial nodes [n_rad]; others: {1.0}
     hsd::DevBuf d_nodes;                      // EXPLICIT/CUBE: [n*3]
+    int32_t cube_M = 0;                       // CUBE: lattice indices -M/2..M/2 per axis
+    double cube_h = 0.0;                      // CUBE: lattice spacing 2 xi_max / M
     // per-s tables, kept for the rule's lifetime (requests with different s
     // may run concurrently): SP -> radial [n_rad]; general -> per node [n]
     struct Tables {

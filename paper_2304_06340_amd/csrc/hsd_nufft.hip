@@ -20,11 +20,15 @@
 //
 // The spread is a gather (one thread per grid point, points visited in a
 // fixed bin-sorted order), so it is deterministic without atomics on
-// floating-point values; the binning uses integer atomics for counts and
-// placement and then sorts each bin by point index.
+// floating-point values; the points are ordered by a stable radix sort on
+// their bin (rocPRIM), which keeps ascending point index inside each bin
+// (bin sizes range from a few points to tens of thousands when a lattice
+// rule packs a whole mesh into a few bins, so a per-bin sort would not do).
 #include <algorithm>
 #include <cmath>
 #include <vector>
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "hsd_fft.hpp"
 #include "hsd_internal.hpp"
@@ -105,27 +109,10 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const int *__restrict__ count
     for (int i = 0; i < per && b + i < n; ++i) { offs[b + i] = run; run += counts[b + i]; }
 }
 
-__global__ void k_bin_place(const int *__restrict__ keys, int64_t np, const int *__restrict__ offs,
-                            int *__restrict__ cursor, int *__restrict__ perm)
+__global__ void k_iota(int *__restrict__ idx, int64_t np)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= np) return;
-    const int k = keys[i];
-    perm[offs[k] + atomicAdd(&cursor[k], 1)] = (int)i;
-}
-
-// Canonical order inside each bin: ascending point index (insertion sort).
-__global__ void k_bin_sort(const int *__restrict__ offs, int nbins, int *__restrict__ perm)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbins) return;
-    const int lo = offs[b], hi = offs[b + 1];
-    for (int i = lo + 1; i < hi; ++i) {
-        const int v = perm[i];
-        int j = i - 1;
-        while (j >= lo && perm[j] > v) { perm[j + 1] = perm[j]; --j; }
-        perm[j + 1] = v;
-    }
+    if (i < np) idx[i] = (int)i;
 }
 
 __global__ void k_gather_points(const double4 *__restrict__ pts, const int *__restrict__ perm, int64_t np,
@@ -266,6 +253,28 @@ __global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine
 }
 
 // --------------------------------------------------------------------------
+// 4'. type 1 (lattice targets): read the transformed grid at the lattice
+//     index of each node and divide by the kernel's transform
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_lattice_out(const double2 *__restrict__ fine, int n,
+                                                     const double *__restrict__ nodes, int64_t N, double inv_h,
+                                                     int M, const double *__restrict__ dec, double2 *__restrict__ out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    int64_t idx = 0;
+    double f = 1.0;
+    for (int a = 0; a < 3; ++a) {
+        int k = (int)__builtin_rint(nodes[3 * q + a] * inv_h);
+        k = k < -M / 2 ? -M / 2 : (k > M / 2 ? M / 2 : k);
+        f *= dec[k + M / 2];
+        idx = idx * n + (k < 0 ? k + n : k);
+    }
+    const double2 v = fine[idx];
+    out[q] = make_double2(v.x * f, v.y * f);
+}
+
+// --------------------------------------------------------------------------
 // host driver
 // --------------------------------------------------------------------------
 static void tri_rule_table(int kind, std::vector<double4> &tab)
@@ -378,10 +387,23 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
         for (double v : rule->host_nodes) S = std::max(S, std::fabs(v));
     }
     S = std::max(S, 1e-3);
-    const double h1 = kPi / (sigma * S);
-    int n1 = (int)std::ceil(2.0 * X / h1 + w + 2);
+    // Lattice targets (cube trapezoid rule, xi = h_xi k): type 1.  The sources
+    // scaled to t = h_xi x must lie inside (-pi, pi) with the kernel's support
+    // on a grid of n >= sigma (M+1) points per axis; then one grid serves as
+    // spread grid and FFT grid, and the transform is read at the lattice
+    // indices (no interpolation stage).  Otherwise (or if they do not fit):
+    // type 3 as described above.
+    bool lattice = false;
+    int nl = 0;
+    if (rule->kind == HSD_RULE_CUBE_TRAPEZOID && rule->cube_M > 0) {
+        nl = 2 * fft_next_size((int)std::ceil(0.5 * sigma * (rule->cube_M + 1)));
+        lattice = fft_size_ok(nl) && nl <= 2048 &&
+                  X * nl * rule->cube_h / (2.0 * kPi) + 0.5 * w + 2.0 <= 0.5 * nl;
+    }
+    const double h1 = lattice ? 2.0 * kPi / (nl * rule->cube_h) : kPi / (sigma * S);
+    int n1 = lattice ? nl : (int)std::ceil(2.0 * X / h1 + w + 2);
     n1 += n1 & 1;
-    const int n2 = fft_next_size((int)std::ceil(sigma * n1));
+    const int n2 = lattice ? nl : fft_next_size((int)std::ceil(sigma * n1));
     if (!fft_size_ok(n2) || n2 > 2048) {
         set_error("NUFFT grid %d^3 exceeds the supported FFT size (2048)", n2);
         return HSD_EINVAL;
@@ -396,20 +418,33 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     // kernel-transform tables
     std::vector<double2> ftq;
     es_ft_table(beta, 4 * w + 24, ftq);
-    std::vector<double> hinv(n1);
-    for (int l = 0; l < n1; ++l) {
-        const int lp = l - n1 / 2;
-        // H^_l = (1/2pi) int h(t) e^{-ilt} dt with h(t) = psi(t n2 / (pi w))
-        const double Hl = (double)w / (2.0 * n2) * es_ft_host(ftq, lp * w * kPi / n2);
-        hinv[l] = 1.0 / Hl;
+    std::vector<double> hinv(n1, 1.0), dec;
+    if (!lattice) {
+        for (int l = 0; l < n1; ++l) {
+            const int lp = l - n1 / 2;
+            // H^_l = (1/2pi) int h(t) e^{-ilt} dt with h(t) = psi(t n2 / (pi w))
+            const double Hl = (double)w / (2.0 * n2) * es_ft_host(ftq, lp * w * kPi / n2);
+            hinv[l] = 1.0 / Hl;
+        }
+    } else {
+        // spreading with phi(t) = psi(t n / (pi w)) on spacing 2 pi / n gives
+        // sum_l b_l e^{-ik t_l} = (n / 2 pi)^3 prod phi^(k_a) sum_j c_j e^{-ik.t_j},
+        // phi^(k) = (pi w / n) int_{-1}^{1} psi(z) e^{-i k (pi w / n) z} dz
+        const int M = rule->cube_M;
+        dec.resize((size_t)M + 1);
+        for (int k = -M / 2; k <= M / 2; ++k)
+            dec[(size_t)(k + M / 2)] = 2.0 / ((double)w * es_ft_host(ftq, k * kPi * w / n1));
     }
     const int64_t N = rule->n_nodes;
     if ((stt = sc.tri.alloc(ctx, trule.size() * sizeof(double4))) != HSD_OK) return stt;
     if ((stt = sc.ftq.alloc(ctx, ftq.size() * sizeof(double2))) != HSD_OK) return stt;
-    if ((stt = sc.hinv.alloc(ctx, hinv.size() * sizeof(double))) != HSD_OK) return stt;
+    if ((stt = sc.hinv.alloc(ctx, (hinv.size() + dec.size()) * sizeof(double))) != HSD_OK) return stt;
     HSD_HIP_TRY(hipMemcpyAsync(sc.tri.ptr, trule.data(), trule.size() * sizeof(double4), hipMemcpyHostToDevice, st));
     HSD_HIP_TRY(hipMemcpyAsync(sc.ftq.ptr, ftq.data(), ftq.size() * sizeof(double2), hipMemcpyHostToDevice, st));
     HSD_HIP_TRY(hipMemcpyAsync(sc.hinv.ptr, hinv.data(), hinv.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    if (!dec.empty())
+        HSD_HIP_TRY(hipMemcpyAsync(sc.hinv.as<double>() + hinv.size(), dec.data(), dec.size() * sizeof(double),
+                                   hipMemcpyHostToDevice, st));
     auto ens = [&](DevBuf &b, size_t bytes) -> hsd_status {
         if (b.ptr && b.bytes >= bytes) return HSD_OK;
         return b.alloc(ctx, std::max<size_t>(bytes, 8));
@@ -417,9 +452,17 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     if ((stt = ens(sc.pts, (size_t)np * sizeof(double4))) != HSD_OK) return stt;
     if ((stt = ens(sc.spts, (size_t)np * sizeof(double4))) != HSD_OK) return stt;
     if ((stt = ens(sc.keys, (size_t)np * sizeof(int))) != HSD_OK) return stt;
+    if ((stt = ens(sc.keys2, (size_t)np * sizeof(int))) != HSD_OK) return stt;
+    if ((stt = ens(sc.iota, (size_t)np * sizeof(int))) != HSD_OK) return stt;
     if ((stt = ens(sc.perm, (size_t)np * sizeof(int))) != HSD_OK) return stt;
     if ((stt = ens(sc.counts, (size_t)nbins * sizeof(int))) != HSD_OK) return stt;
-    if ((stt = ens(sc.cursor, (size_t)nbins * sizeof(int))) != HSD_OK) return stt;
+    int key_bits = 1;
+    while ((1 << key_bits) < nbins) ++key_bits;
+    size_t sort_bytes = 0;
+    HSD_HIP_TRY(rocprim::radix_sort_pairs(nullptr, sort_bytes, sc.keys.as<int>(), sc.keys2.as<int>(),
+                                          sc.iota.as<int>(), sc.perm.as<int>(), (unsigned int)np, 0, key_bits,
+                                          st));
+    if ((stt = ens(sc.sorttmp, sort_bytes)) != HSD_OK) return stt;
     if ((stt = ens(sc.offs, ((size_t)nbins + 1) * sizeof(int))) != HSD_OK) return stt;
     if ((stt = ens(sc.grid1, (size_t)n1 * n1 * n1 * sizeof(double))) != HSD_OK) return stt;
     if ((stt = ens(sc.fine, (size_t)n2 * n2 * n2 * sizeof(double2))) != HSD_OK) return stt;
@@ -433,7 +476,6 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     const TriRec *B = nu ? nu->tris.as<const TriRec>() : nullptr;
     const int64_t nB = nu ? nu->nt : 0;
     HSD_HIP_TRY(hipMemsetAsync(sc.counts.ptr, 0, (size_t)nbins * sizeof(int), st));
-    HSD_HIP_TRY(hipMemsetAsync(sc.cursor.ptr, 0, (size_t)nbins * sizeof(int), st));
     if (np > 0) {
         const unsigned g = (unsigned)((np + 255) / 256);
         hipLaunchKernelGGL(k_nufft_points, dim3(g), dim3(256), 0, st, A, mu->nt, B, nB, sc.tri.as<const double4>(), nq,
@@ -446,12 +488,11 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     HSD_HIP_TRY(hipGetLastError());
     if (np > 0) {
         const unsigned g = (unsigned)((np + 255) / 256);
-        hipLaunchKernelGGL(k_bin_place, dim3(g), dim3(256), 0, st, sc.keys.as<const int>(), np, sc.offs.as<const int>(),
-                           sc.cursor.as<int>(), sc.perm.as<int>());
+        hipLaunchKernelGGL(k_iota, dim3(g), dim3(256), 0, st, sc.iota.as<int>(), np);
         HSD_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_bin_sort, dim3((nbins + 255) / 256), dim3(256), 0, st, sc.offs.as<const int>(), nbins,
-                           sc.perm.as<int>());
-        HSD_HIP_TRY(hipGetLastError());
+        HSD_HIP_TRY(rocprim::radix_sort_pairs(sc.sorttmp.ptr, sort_bytes, sc.keys.as<int>(), sc.keys2.as<int>(),
+                                              sc.iota.as<int>(), sc.perm.as<int>(), (unsigned int)np, 0, key_bits,
+                                              st));
         hipLaunchKernelGGL(k_gather_points, dim3(g), dim3(256), 0, st, sc.pts.as<const double4>(),
                            sc.perm.as<const int>(), np, sc.spts.as<double4>());
         HSD_HIP_TRY(hipGetLastError());
@@ -464,6 +505,14 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
                        n1, sc.hinv.as<const double>(), n2, sc.fine.as<double2>());
     HSD_HIP_TRY(hipGetLastError());
     if ((stt = fft3d_forward(st, plan, sc.fine.as<double2>())) != HSD_OK) return stt;
+    if (lattice) {
+        hipLaunchKernelGGL(k_lattice_out, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                           sc.fine.as<const double2>(), n2, rule->d_nodes.as<const double>(), N, 1.0 / rule->cube_h,
+                           rule->cube_M, sc.hinv.as<const double>() + hinv.size(), out);
+        HSD_HIP_TRY(hipGetLastError());
+        if (pairs) *pairs = (double)np;
+        return HSD_OK;
+    }
     const double *dirs = sp ? rule->d_dirs.as<const double>() : rule->d_nodes.as<const double>();
     const int n_rad = sp ? (int)rule->n_rad : 1;
     hipLaunchKernelGGL(k_interp, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, sc.fine.as<const double2>(), n2,

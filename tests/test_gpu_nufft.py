@@ -100,3 +100,53 @@ def test_nufft_distance_model_error_and_determinism(hsd_ctx, orc):
                     mu = orc.point_sum(pts, c, o.nodes)
                     d2_pts = math.fsum(W * np.abs(mu - nu) ** 2)
                     assert abs(r1.d2 - d2_pts) <= 1e-6 * d2_pts, (r1.d2, d2_pts)
+
+
+@pytest.mark.parametrize("tri_rule", ["dunavant7", "gl8x8"])
+@pytest.mark.parametrize("xi_max,M", [(10.0, 32), (12.0, 30), (40.0, 8)])
+def test_nufft_lattice_targets(hsd_ctx, orc, tri_rule, xi_max, M):
+    """Cube trapezoid rules put the targets on a lattice xi = h k: the NUFFT
+    runs as type 1 (spread, FFT, read at the lattice indices) when the scaled
+    sources h x fit inside (-pi, pi) with the kernel's support; the last case
+    (h = 10) does not fit and takes the type-3 path.  Both against the
+    oracle's direct sum over the same point cloud."""
+    rng = np.random.default_rng(11)
+    v, f = icosphere(2)
+    v = rotate(perturb_radial(v, 0.01, rng), random_rotation(rng))
+    rule = hsd.Rule.cube_trapezoid(hsd_ctx, xi_max, M)
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    p = hsd.Params(method="nufft3", tri_rule=tri_rule, nufft_tol=1e-10)
+    got = hsd.transform_rule(hsd_ctx, mesh, rule, p)
+    o = orc.cube_trapezoid_rule(xi_max, M)
+    pts, c = orc.point_cloud(v, f, tri_rule)
+    ref = orc.point_sum(pts, c, o.nodes)
+    err = np.max(np.abs(got - ref)) / np.sum(np.abs(c))
+    print(f"lattice xi_max={xi_max} M={M} {tri_rule}: max |err| / sum|c| = {err:.2e}")
+    assert err <= 1e-10
+    mesh.close()
+    rule.close()
+
+
+def test_nufft_paper_configuration(hsd_ctx, orc):
+    """The paper's own setting (section 4, Figs. 3(b) and 4): exp(-2 pi i eta.x)
+    convention, order -10, trapezoid rule xi_max = 5, M = 128, 64-point GL
+    triangle rule.  The lattice NUFFT d^2 against the exact-triangle direct
+    d^2 (level 4: the GL 8x8 model error is far below 1e-6), and the empty
+    surface against eq. sphere_sobolev_exact."""
+    xi = 2 * math.pi * 5.0
+    rule = hsd.Rule.cube_trapezoid(hsd_ctx, xi, 128)
+    v, f = icosphere(4)
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    pn = hsd.Params(s=10.0, freq_unit=2 * math.pi, method="nufft3", tri_rule="gl8x8", nufft_tol=1e-12)
+    pd = hsd.Params(s=10.0, freq_unit=2 * math.pi)
+    dn = hsd.distance(hsd_ctx, mesh, None, rule, pn)
+    dd = hsd.distance(hsd_ctx, mesh, None, rule, pd)
+    print(f"paper configuration, level 4: nufft d2 {dn.d2:.12e} ({dn.transform_ms:.2f} ms), "
+          f"direct d2 {dd.d2:.12e} ({dd.transform_ms:.1f} ms)")
+    assert abs(dn.d2 - dd.d2) <= 1e-6 * dd.d2
+    empty = hsd.Mesh(hsd_ctx, np.zeros((0, 3)), np.zeros((0, 3), np.int32))
+    e = hsd.distance(hsd_ctx, empty, None, rule, pn).d2
+    assert abs(e - orc.sphere_norm_paper(-10.0)) <= 1e-12 * e
+    empty.close()
+    mesh.close()
+    rule.close()
