@@ -73,7 +73,7 @@ struct Scratch {
 // or by a serving slot).
 struct FftPlan;
 struct NufftScratch {
-    DevBuf pts, spts, keys, keys2, iota, counts, offs, perm, sorttmp, grid1, fine, tri, ftq, hinv;
+    DevBuf pts, spts, keys, keys2, iota, offs, perm, sorttmp, grid1, fine, tri, ftq, hinv;
     std::unique_ptr<FftPlan> plan;
     NufftScratch();
     ~NufftScratch();

@@ -83,30 +83,16 @@ __global__ void k_nufft_points(const TriRec *__restrict__ A, int64_t nA, const T
     keys[gid] = (b[0] * nbx + b[1]) * nbx + b[2];
 }
 
-__global__ void k_bin_count(const int *__restrict__ keys, int64_t np, int *__restrict__ counts)
+// Bin offsets from the sorted keys: offs[b] = first position whose key is
+// >= b (offs[nbins] = np).  Position i writes the bins in (key[i-1], key[i]],
+// so every entry has exactly one writer.
+__global__ void k_bin_offsets(const int *__restrict__ skeys, int64_t np, int nbins, int *__restrict__ offs)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < np) atomicAdd(&counts[keys[i]], 1);
-}
-
-// Exclusive scan of counts[n] into offs[n+1] by one block (fixed order).
-__global__ __launch_bounds__(1024) void k_bin_scan(const int *__restrict__ counts, int n, int *__restrict__ offs)
-{
-    __shared__ int part[1024];
-    const int per = (n + 1023) / 1024;
-    const int b = threadIdx.x * per;
-    int s = 0;
-    for (int i = 0; i < per && b + i < n; ++i) s += counts[b + i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int i = 0; i < 1024; ++i) { const int v = part[i]; part[i] = run; run += v; }
-        offs[n] = run;
-    }
-    __syncthreads();
-    int run = part[threadIdx.x];
-    for (int i = 0; i < per && b + i < n; ++i) { offs[b + i] = run; run += counts[b + i]; }
+    if (i > np) return;
+    const int prev = i == 0 ? -1 : skeys[i - 1];
+    const int cur = i == np ? nbins : skeys[i];
+    for (int b = prev + 1; b <= cur; ++b) offs[b] = (int)i;
 }
 
 __global__ void k_iota(int *__restrict__ idx, int64_t np)
@@ -123,7 +109,11 @@ __global__ void k_gather_points(const double4 *__restrict__ pts, const int *__re
 }
 
 // --------------------------------------------------------------------------
-// 2. spread (gather form): block = one 8x8x8 tile of grid points
+// 2. spread (gather form): block = one 8x8x8 tile of grid points.  The
+//    points of the 27 bins around the tile are staged in chunks of 64 (one
+//    wavefront loads a chunk); only those whose kernel support reaches the
+//    tile are kept (ballot compaction, order preserved), so a point costs
+//    work only in the tiles it touches.  Sum order: bin, then point order.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(512) void k_spread(const double4 *__restrict__ spts, const int *__restrict__ offs,
                                                 int nbx, int n1, double h1, double half_w, double beta,
@@ -132,11 +122,13 @@ __global__ __launch_bounds__(512) void k_spread(const double4 *__restrict__ spts
     __shared__ double kv[kChunk][3 * kBin];
     __shared__ double cw[kChunk];
     __shared__ double gc[kChunk][3];
+    __shared__ int nkeep;
     const int tx = threadIdx.x & 7, ty = (threadIdx.x >> 3) & 7, tz = threadIdx.x >> 6;
     const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
     const int org[3] = {bx * kBin, by * kBin, bz * kBin};
     const double half = 0.5 * n1;
     const double iw = 1.0 / half_w;
+    const int lane = threadIdx.x & 63;
     double acc = 0.0;
     for (int dx = -1; dx <= 1; ++dx)
         for (int dy = -1; dy <= 1; ++dy)
@@ -147,22 +139,42 @@ __global__ __launch_bounds__(512) void k_spread(const double4 *__restrict__ spts
                 const int lo = offs[nb], hi = offs[nb + 1];
                 for (int c0 = lo; c0 < hi; c0 += kChunk) {
                     const int cnt = (hi - c0) < kChunk ? (hi - c0) : kChunk;
-                    if ((int)threadIdx.x < cnt) {
-                        const double4 p = spts[c0 + threadIdx.x];
-                        gc[threadIdx.x][0] = p.x / h1 + half;
-                        gc[threadIdx.x][1] = p.y / h1 + half;
-                        gc[threadIdx.x][2] = p.z / h1 + half;
-                        cw[threadIdx.x] = p.w;
+                    if (threadIdx.x < kChunk) {
+                        bool keep = false;
+                        double g[3] = {0.0, 0.0, 0.0}, wv = 0.0;
+                        if (lane < cnt) {
+                            const double4 p = spts[c0 + lane];
+                            g[0] = p.x / h1 + half;
+                            g[1] = p.y / h1 + half;
+                            g[2] = p.z / h1 + half;
+                            wv = p.w;
+                            keep = true;
+                            for (int d = 0; d < 3; ++d)
+                                keep = keep && g[d] > (double)org[d] - half_w - 1.0 &&
+                                       g[d] < (double)(org[d] + kBin - 1) + half_w + 1.0;
+                        }
+                        const unsigned long long m = __ballot(keep);
+                        if (keep) {
+                            const int pos = __popcll(m & ((1ull << lane) - 1ull));
+                            gc[pos][0] = g[0];
+                            gc[pos][1] = g[1];
+                            gc[pos][2] = g[2];
+                            cw[pos] = wv;
+                        }
+                        if (lane == 0) nkeep = __popcll(m);
                     }
                     __syncthreads();
-                    for (int v = threadIdx.x; v < cnt * 3 * kBin; v += 512) {
-                        const int p = v / (3 * kBin), r = v - p * (3 * kBin);
-                        const int d = r / kBin, i = r - d * kBin;
-                        kv[p][r] = es_eval(((double)(org[d] + i) - gc[p][d]) * iw, beta);
+                    const int nk = nkeep;
+                    if (nk > 0) {
+                        for (int v = threadIdx.x; v < nk * 3 * kBin; v += 512) {
+                            const int p = v / (3 * kBin), r = v - p * (3 * kBin);
+                            const int d = r / kBin, i = r - d * kBin;
+                            kv[p][r] = es_eval(((double)(org[d] + i) - gc[p][d]) * iw, beta);
+                        }
+                        __syncthreads();
+                        for (int p = 0; p < nk; ++p)
+                            acc = __builtin_fma(cw[p] * kv[p][tx], kv[p][kBin + ty] * kv[p][2 * kBin + tz], acc);
                     }
-                    __syncthreads();
-                    for (int p = 0; p < cnt; ++p)
-                        acc = __builtin_fma(cw[p] * kv[p][tx], kv[p][kBin + ty] * kv[p][2 * kBin + tz], acc);
                     __syncthreads();
                 }
             }
@@ -455,7 +467,6 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     if ((stt = ens(sc.keys2, (size_t)np * sizeof(int))) != HSD_OK) return stt;
     if ((stt = ens(sc.iota, (size_t)np * sizeof(int))) != HSD_OK) return stt;
     if ((stt = ens(sc.perm, (size_t)np * sizeof(int))) != HSD_OK) return stt;
-    if ((stt = ens(sc.counts, (size_t)nbins * sizeof(int))) != HSD_OK) return stt;
     int key_bits = 1;
     while ((1 << key_bits) < nbins) ++key_bits;
     size_t sort_bytes = 0;
@@ -475,19 +486,11 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     const TriRec *A = mu->tris.as<const TriRec>();
     const TriRec *B = nu ? nu->tris.as<const TriRec>() : nullptr;
     const int64_t nB = nu ? nu->nt : 0;
-    HSD_HIP_TRY(hipMemsetAsync(sc.counts.ptr, 0, (size_t)nbins * sizeof(int), st));
     if (np > 0) {
         const unsigned g = (unsigned)((np + 255) / 256);
         hipLaunchKernelGGL(k_nufft_points, dim3(g), dim3(256), 0, st, A, mu->nt, B, nB, sc.tri.as<const double4>(), nq,
                            h1, n1, nbx, sc.pts.as<double4>(), sc.keys.as<int>());
         HSD_HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(256), 0, st, sc.keys.as<const int>(), np, sc.counts.as<int>());
-        HSD_HIP_TRY(hipGetLastError());
-    }
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, sc.counts.as<const int>(), nbins, sc.offs.as<int>());
-    HSD_HIP_TRY(hipGetLastError());
-    if (np > 0) {
-        const unsigned g = (unsigned)((np + 255) / 256);
         hipLaunchKernelGGL(k_iota, dim3(g), dim3(256), 0, st, sc.iota.as<int>(), np);
         HSD_HIP_TRY(hipGetLastError());
         HSD_HIP_TRY(rocprim::radix_sort_pairs(sc.sorttmp.ptr, sort_bytes, sc.keys.as<int>(), sc.keys2.as<int>(),
@@ -497,6 +500,9 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
                            sc.perm.as<const int>(), np, sc.spts.as<double4>());
         HSD_HIP_TRY(hipGetLastError());
     }
+    hipLaunchKernelGGL(k_bin_offsets, dim3((unsigned)((np + 1 + 255) / 256)), dim3(256), 0, st,
+                       sc.keys2.as<const int>(), np, nbins, sc.offs.as<int>());
+    HSD_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_spread, dim3(nbx, nbx, nbx), dim3(512), 0, st, sc.spts.as<const double4>(),
                        sc.offs.as<const int>(), nbx, n1, h1, 0.5 * w, beta, sc.grid1.as<double>());
     HSD_HIP_TRY(hipGetLastError());
