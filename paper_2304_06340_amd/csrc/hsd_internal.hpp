@@ -151,6 +151,14 @@ struct hsd_rule {
         hsd::DevBuf nu;                       // sphere transform 4 pi sin r / r
     };
     std::map<std::pair<double, double>, std::unique_ptr<Tables>> tabs;   // by (s, freq_unit)
+    // per-node 1 / Phi^(xi_k) of the type-3 NUFFT, by (width, beta, h1): it
+    // depends on the rule and the kernel only, not on the mesh
+    struct NufftDeconv {
+        int w = 0;
+        double beta = 0.0, h1 = 0.0;
+        hsd::DevBuf inv;
+    };
+    std::vector<std::unique_ptr<NufftDeconv>> nufft_deconv;
     std::mutex mu;
     std::atomic<int> refs{1};
     ~hsd_rule();

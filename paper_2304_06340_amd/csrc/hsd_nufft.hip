@@ -208,11 +208,13 @@ __global__ void k_predeconv(const double *__restrict__ grid, int n1, const doubl
 // --------------------------------------------------------------------------
 // 4. interpolate at the targets and divide by Phi^
 // --------------------------------------------------------------------------
+template <int W>
 __global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine, int n2, const double *__restrict__ dirs,
                                                 const double *__restrict__ radii, int n_rad, int64_t N, double h1,
-                                                int w, double beta, const double2 *__restrict__ ftq, int nq,
+                                                double beta, const double *__restrict__ phi_inv,
                                                 double2 *__restrict__ out)
 {
+    constexpr int w = W;   // kernel width: compile-time so the gathers unroll
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
     const int64_t d = k / n_rad;
@@ -222,7 +224,7 @@ __global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine
     const double half_w = 0.5 * w;
     const double iw = 1.0 / half_w;
     const double scale = (double)n2 * h1 / (2.0 * kPi);
-    double wt[3][kMaxW];
+    double wt[3][W];
     int base[3];
     for (int a = 0; a < 3; ++a) {
         const double u = xi[a] * scale;
@@ -230,19 +232,24 @@ __global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine
         base[a] = lo;
         for (int i = 0; i < w; ++i) wt[a][i] = es_eval(((double)(lo + i) - u) * iw, beta);
     }
+    // periodic grid indices: wrap each axis' first index once, then step by
+    // one with wrap-around
+    int start[3];
+    for (int a = 0; a < 3; ++a) {
+        int b0 = base[a] % n2;
+        start[a] = b0 < 0 ? b0 + n2 : b0;
+    }
     double re = 0.0, im = 0.0;
-    for (int i = 0; i < w; ++i) {
-        int mx = (base[0] + i) % n2;
-        if (mx < 0) mx += n2;
-        for (int j = 0; j < w; ++j) {
-            int my = (base[1] + j) % n2;
-            if (my < 0) my += n2;
+    int mx = start[0];
+    for (int i = 0; i < w; ++i, mx = (mx + 1 == n2 ? 0 : mx + 1)) {
+        int my = start[1];
+        for (int j = 0; j < w; ++j, my = (my + 1 == n2 ? 0 : my + 1)) {
             const double wxy = wt[0][i] * wt[1][j];
             const double2 *row = fine + ((int64_t)mx * n2 + my) * n2;
             double sre = 0.0, sim = 0.0;
-            for (int l = 0; l < w; ++l) {
-                int mz = (base[2] + l) % n2;
-                if (mz < 0) mz += n2;
+            int mz = start[2];
+#pragma unroll
+            for (int l = 0; l < w; ++l, mz = (mz + 1 == n2 ? 0 : mz + 1)) {
                 const double2 v = row[mz];
                 sre = __builtin_fma(v.x, wt[2][l], sre);
                 sim = __builtin_fma(v.y, wt[2][l], sim);
@@ -251,17 +258,31 @@ __global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine
             im = __builtin_fma(sim, wxy, im);
         }
     }
-    // Phi^(xi) = prod_a (w h1 / 2) 2 sum_q wpsi_q cos(xi_a (w h1 / 2) z_q)
+    const double n2d = (double)n2;
+    const double f = h1 * h1 * h1 / (n2d * n2d * n2d) * phi_inv[k];
+    out[k] = make_double2(re * f, im * f);
+}
+
+// 1 / Phi^(xi_k) per node, Phi^(xi) = prod_a (w h1 / 2) 2 sum_q wpsi_q
+// cos(xi_a (w h1 / 2) z_q) (Gauss-Legendre quadrature of psi's transform).
+__global__ __launch_bounds__(256) void k_phi_inv(const double *__restrict__ dirs, const double *__restrict__ radii,
+                                                 int n_rad, int64_t N, double h1, int w,
+                                                 const double2 *__restrict__ ftq, int nq, double *__restrict__ phi_inv)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int64_t d = k / n_rad;
+    const int ir = (int)(k - d * n_rad);
+    const double r = radii[ir];
     double phi = 1.0;
     const double hw = 0.5 * w * h1;
     for (int a = 0; a < 3; ++a) {
+        const double xa = r * dirs[3 * d + a];
         double s = 0.0;
-        for (int q = 0; q < nq; ++q) s += ftq[q].y * sincos64(xi[a] * hw * ftq[q].x).c;
+        for (int q = 0; q < nq; ++q) s += ftq[q].y * sincos64(xa * hw * ftq[q].x).c;
         phi *= hw * 2.0 * s;
     }
-    const double n2d = (double)n2;
-    const double f = h1 * h1 * h1 / (n2d * n2d * n2d) / phi;
-    out[k] = make_double2(re * f, im * f);
+    phi_inv[k] = 1.0 / phi;
 }
 
 // --------------------------------------------------------------------------
@@ -521,9 +542,41 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     }
     const double *dirs = sp ? rule->d_dirs.as<const double>() : rule->d_nodes.as<const double>();
     const int n_rad = sp ? (int)rule->n_rad : 1;
-    hipLaunchKernelGGL(k_interp, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, sc.fine.as<const double2>(), n2,
-                       dirs, rule->d_radii.as<const double>(), n_rad, N, h1, w, beta, sc.ftq.as<const double2>(),
-                       (int)ftq.size(), out);
+    const double *phi_inv = nullptr;
+    {
+        hsd_rule *rm = const_cast<hsd_rule *>(rule);
+        std::lock_guard<std::mutex> lk(rm->mu);
+        for (const auto &e : rm->nufft_deconv)
+            if (e->w == w && e->beta == beta && e->h1 == h1) phi_inv = e->inv.as<const double>();
+        if (!phi_inv) {
+            std::unique_ptr<hsd_rule::NufftDeconv> e(new hsd_rule::NufftDeconv());
+            e->w = w;
+            e->beta = beta;
+            e->h1 = h1;
+            if ((stt = e->inv.alloc(ctx, (size_t)N * sizeof(double))) != HSD_OK) return stt;
+            hipLaunchKernelGGL(k_phi_inv, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, dirs,
+                               rule->d_radii.as<const double>(), n_rad, N, h1, w, sc.ftq.as<const double2>(),
+                               (int)ftq.size(), e->inv.as<double>());
+            HSD_HIP_TRY(hipGetLastError());
+            // complete before other streams (serving slots) may read it
+            HSD_HIP_TRY(hipStreamSynchronize(st));
+            phi_inv = e->inv.as<const double>();
+            rm->nufft_deconv.push_back(std::move(e));
+        }
+    }
+    const dim3 ig((unsigned)((N + 255) / 256)), ib(256);
+    const double2 *fg = sc.fine.as<const double2>();
+    const double *rr = rule->d_radii.as<const double>();
+    switch (w) {
+#define HSD_INTERP_W(WW)                                                                                        \
+    case WW: hipLaunchKernelGGL(k_interp<WW>, ig, ib, 0, st, fg, n2, dirs, rr, n_rad, N, h1, beta, phi_inv, out); \
+        break;
+        HSD_INTERP_W(2) HSD_INTERP_W(3) HSD_INTERP_W(4) HSD_INTERP_W(5) HSD_INTERP_W(6) HSD_INTERP_W(7)
+        HSD_INTERP_W(8) HSD_INTERP_W(9) HSD_INTERP_W(10) HSD_INTERP_W(11) HSD_INTERP_W(12) HSD_INTERP_W(13)
+        HSD_INTERP_W(14) HSD_INTERP_W(15) HSD_INTERP_W(16)
+#undef HSD_INTERP_W
+    default: set_error("NUFFT width %d unsupported", w); return HSD_EINVAL;
+    }
     HSD_HIP_TRY(hipGetLastError());
     if (pairs) *pairs = (double)np;
     return HSD_OK;
