@@ -126,8 +126,16 @@ HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, i
     for (int c = 0; c < 3; ++c) {
         Bk[c] = sincos64_tab(hx * fr[c], turn);
         P0[c] = sincos64_tab(r0 * fr[c], turn);
+        Cp[0][c] = sincos64_tab((double)(2 * (w0 + j * PG) + 1) * h * fr[c], turn);
+        if (PG > 1) {
+            // next panel centre: times e^{-2ihc} = (e^{-i hx c} e^{-i (h - hx) c})^2,
+            // three products instead of a sin/cos (all angles of one sign add,
+            // so small angles keep their relative accuracy)
+            const cs64 e1 = pmul(Bk[c], P0[c]);
+            const cs64 step = pmul(e1, e1);
 #pragma unroll
-        for (int q = 0; q < PG; ++q) Cp[q][c] = sincos64_tab((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c], turn);
+            for (int q = 1; q < PG; ++q) Cp[q][c] = pmul(Cp[q - 1][c], step);
+        }
     }
     if (sc) {
         sc->Ka = 2.0 * td.J * rcp64(td.ac) * td.iG;
@@ -263,6 +271,16 @@ HSD_HD void consume32(const Scal32 &sc, const cs32 Bk[3], const cs32 P0[3], cons
     }
 }
 
+// Each wave produces and consumes its own LDS batch, so the two steps only
+// need ordering among the lanes of that wave: a wavefront-scope fence (the
+// compiler waits for the wave's LDS writes before its later reads).  Waves of
+// a block never wait for each other.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 HSD_HD const TriRec *tri_at(const TriRec *A, int64_t nA, const TriRec *B, int64_t gi, double &J)
 {
     const bool inA = gi < nA;
@@ -330,14 +348,14 @@ __global__ __launch_bounds__(256) void k_direct_wave(
                 produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
                               L.P0[pt][pj], &L.Cp[pt][pj * PG]);
         }
-        __syncthreads();
+        wave_lds_sync();
         for (int t = 0; t < nvalid; ++t) {
             if constexpr (F64)
                 consume64<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx, pfirst, acc_re, acc_im);
             else
                 consume32<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx, pfirst, acc_re, acc_im);
         }
-        __syncthreads();
+        wave_lds_sync();
         if (++nb == kTileBatches) {
             nb = 0;
 #pragma unroll
