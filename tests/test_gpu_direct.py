@@ -275,3 +275,26 @@ def test_paper_convention_mode(hsd_ctx, orc):
     empty.close()
     r64.close()
     r128.close()
+
+
+def test_largest_rule_sampled_nodes(hsd_ctx, orc):
+    """The 67,108,864-node rule (128 GL panels x 16 radial x 128 x 256 on
+    [0, 256]; eight wavefronts share each direction) at 2,048 seeded nodes
+    against the oracle, on a perturbed level-4 mesh (5,120 triangles)."""
+    spec = dict(r_max=256.0, n_panels=128, n_per_panel=16, n_cos=128, n_phi=256)
+    rng = np.random.default_rng(21)
+    v, f = icosphere(4)
+    v = rotate(perturb_radial(v, 0.01, rng), random_rotation(rng))
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    g = hsd.Rule.spherical_product(hsd_ctx, **spec)
+    assert len(g) == 67108864
+    full = hsd.transform_rule(hsd_ctx, mesh, g)
+    idx = np.sort(rng.choice(len(g), size=2048, replace=False))
+    nodes = np.ascontiguousarray(g.nodes()[0][idx])
+    ref = orc.transform(v, f, nodes)
+    err = np.abs(full[idx] - ref)
+    tol = _mu_tol(v, f, nodes, 20.0)
+    print(f"67M-node rule, level 4: max err {err.max():.3e}, max err/tol {np.max(err / tol):.3f}")
+    assert np.all(err <= tol)
+    mesh.close()
+    g.close()
