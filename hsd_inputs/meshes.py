@@ -161,3 +161,28 @@ def random_points(n: int, rng: np.random.Generator, rmax: float) -> np.ndarray:
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     r = rng.uniform(0.0, rmax, size=(n, 1))
     return d * r
+
+
+def ellipsoid_mesh(level: int, a: float, b: float, c: float) -> tuple[np.ndarray, np.ndarray]:
+    """Level-N icosphere stretched to the ellipsoid x^2/a^2 + y^2/b^2 +
+    z^2/c^2 = 1 (vertices on the surface; the inscribed polyhedron)."""
+    v, f = icosphere(level)
+    return v * np.array([a, b, c]), f
+
+
+def torus_mesh(n_u: int, n_v: int, R: float, r: float) -> tuple[np.ndarray, np.ndarray]:
+    """Triangulated torus ((R + r cos v) cos u, (R + r cos v) sin u, r sin v)
+    on an n_u x n_v grid of the parameter square (vertices on the surface),
+    two triangles per cell, consistently oriented."""
+    u = 2.0 * np.pi * np.arange(n_u) / n_u
+    w = 2.0 * np.pi * np.arange(n_v) / n_v
+    U, W = np.meshgrid(u, w, indexing="ij")
+    rho = R + r * np.cos(W)
+    v = np.stack([rho * np.cos(U), rho * np.sin(U), r * np.sin(W)], axis=-1).reshape(-1, 3)
+    i, j = np.meshgrid(np.arange(n_u), np.arange(n_v), indexing="ij")
+    a = i * n_v + j
+    b = ((i + 1) % n_u) * n_v + j
+    c = ((i + 1) % n_u) * n_v + (j + 1) % n_v
+    d = i * n_v + (j + 1) % n_v
+    f = np.concatenate([np.stack([a, b, c], -1).reshape(-1, 3), np.stack([a, c, d], -1).reshape(-1, 3)])
+    return v, f.astype(np.int32)

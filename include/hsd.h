@@ -174,6 +174,44 @@ void hsd_finalize(hsd_ctx *ctx);
 hsd_status hsd_create_mesh(hsd_ctx *ctx, const double *verts, int64_t nv,
                            const int32_t *tris, int64_t nt, int32_t mem_kind,
                            hsd_mesh **out);
+/* A weighted point measure sum_q c_q delta(x - y_q) in place of a mesh: the
+ * target of section 5's extension to smooth parametrised surfaces, sampled
+ * by a quadrature on the parameter domain (points y_q, weights c_q = quadrature
+ * weight times the area element).  Usable wherever a mesh is accepted by
+ * hsd_distance, hsd_transform and hsd_transform_rule (as mu or nu), and as
+ * nu of hsd_distance_grad.  Stored as n degenerate triangles (y_q, y_q, y_q)
+ * with J = 2 c_q, whose exact transform J e[z, z, z] = c_q exp(-i xi.y_q):
+ * the direct-sum and NUFFT kernels take it unchanged.
+ * points: [n][3] FP64, weights: [n] FP64 (finite, any sign), both host or
+ * both device memory per mem_kind, copied; n = 0 gives the zero measure.
+ * hsd_mesh_num_vertices/_triangles return n.
+ * Errors: EINVAL (negative n, NULL arrays, non-finite values, bad mem_kind),
+ * ENOMEM, EDEVICE. */
+hsd_status hsd_create_point_measure(hsd_ctx *ctx, const double *points, const double *weights,
+                                    int64_t n, int32_t mem_kind, hsd_mesh **out);
+/* Smooth surfaces with a built-in parametrisation, as point measures sampled
+ * by a quadrature on the parameter domain that converges spectrally
+ * (section 5: a smooth target known exactly, compared with its
+ * triangulations):
+ *  HSD_SURFACE_ELLIPSOID  x = c0 + (a s cos phi, b s sin phi, c u), u = cos theta,
+ *      s = sqrt(1 - u^2); n_u Gauss-Legendre nodes in u, n_v trapezoid nodes in
+ *      phi; area element sqrt(b^2 c^2 s^2 cos^2 phi + a^2 c^2 s^2 sin^2 phi
+ *      + a^2 b^2 u^2) du dphi (a = b = c = 1: the unit sphere);
+ *  HSD_SURFACE_TORUS  x = c0 + ((a + b cos v) cos u, (a + b cos v) sin u, b sin v)
+ *      (centre-line radius a > b > 0, tube radius b); n_u x n_v trapezoid
+ *      nodes; area element b (a + b cos v) du dv.
+ * Points are ordered u-major.  The result behaves as hsd_create_point_measure's.
+ * Errors: EINVAL (unknown kind, n_u or n_v < 1, non-positive or non-finite
+ * radii, a <= b for the torus), ENOMEM, EDEVICE. */
+enum { HSD_SURFACE_ELLIPSOID = 0, HSD_SURFACE_TORUS = 1 };
+typedef struct {
+    int32_t kind;        /* HSD_SURFACE_*                                        */
+    int32_t n_u, n_v;    /* quadrature sizes                                     */
+    double a, b, c;      /* ellipsoid semi-axes; torus: a, b as above (c unused) */
+    double center[3];    /* translation c0                                       */
+    int32_t reserved[4];
+} hsd_surface_desc;
+hsd_status hsd_create_surface_measure(hsd_ctx *ctx, const hsd_surface_desc *desc, hsd_mesh **out);
 int64_t hsd_mesh_num_triangles(const hsd_mesh *m);
 int64_t hsd_mesh_num_vertices(const hsd_mesh *m);
 void hsd_mesh_destroy(hsd_mesh *m);

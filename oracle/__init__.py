@@ -32,6 +32,10 @@ Pieces, each citing what it follows:
     change_variable and change_variable_approx (Section 3.1).
   * ``point_sum``                 -- eq. def_nufft_type1 summed directly.
   * ``sphere_norm_paper``         -- eq. sphere_sobolev_exact (Section 4.1).
+  * ``surface_points``            -- a smooth parametrised surface's measure
+    sampled on its parameter domain (the extension closing Section 5): area
+    element |x_theta x x_phi| from the partial derivatives, Gauss-Legendre in
+    cos(theta) or trapezoid in periodic parameters.
 
 Parity status: every function here is pinned by the CPU tests
 (``tests/test_oracle_*.py``) against closed forms, high-precision brute force
@@ -240,11 +244,13 @@ def transform(verts, tris, nodes, tau: float = TAU_DEFAULT, sign=None) -> np.nda
     return out[0::2] + 1j * out[1::2]
 
 
-def residual(verts, tris, rule: Rule, verts2=None, tris2=None, tau: float = TAU_DEFAULT):
-    """R_k = mu_h^(xi_k) - nu^(xi_k) with nu the unit sphere (verts2 None) or
-    the second mesh."""
+def residual(verts, tris, rule: Rule, verts2=None, tris2=None, tau: float = TAU_DEFAULT, nu_points=None):
+    """R_k = mu_h^(xi_k) - nu^(xi_k) with nu the unit sphere (verts2 None),
+    the second mesh, or a weighted point measure nu_points = (points, c)."""
     mu = transform(verts, tris, rule.nodes, tau)
-    if verts2 is None:
+    if nu_points is not None:
+        nu = point_sum(nu_points[0], nu_points[1], rule.nodes)
+    elif verts2 is None:
         nu = nu_hat_sphere(rule.radii)
     else:
         nu = transform(verts2, tris2, rule.nodes, tau)
@@ -252,10 +258,11 @@ def residual(verts, tris, rule: Rule, verts2=None, tris2=None, tau: float = TAU_
 
 
 def distance(verts, tris, rule: Rule, s: float = 1.0, verts2=None, tris2=None,
-             tau: float = TAU_DEFAULT, return_residual: bool = False, freq_unit: float = 1.0):
+             tau: float = TAU_DEFAULT, return_residual: bool = False, freq_unit: float = 1.0,
+             nu_points=None):
     """d^2 = sum_k W_k |R_k|^2 (eq. sobolev_2 on the quadrature), summed with
     math.fsum in node order."""
-    R = residual(verts, tris, rule, verts2, tris2, tau)
+    R = residual(verts, tris, rule, verts2, tris2, tau, nu_points)
     W = sobolev_weights(rule, s, freq_unit)
     d2 = math.fsum((W * (R.real ** 2 + R.imag ** 2)).tolist())
     return (d2, R) if return_residual else d2
@@ -338,6 +345,55 @@ def point_sum(points, c, nodes) -> np.ndarray:
     out = np.zeros(2 * len(x))
     lib().oracle_point_sum(_dp(p), _dp(cc), len(p), _dp(x), len(x), _dp(out))
     return out[0::2] + 1j * out[1::2]
+
+
+def surface_points(kind: str, n_u: int, n_v: int, a: float = 1.0, b: float = 1.0, c: float = 1.0,
+                   center=(0.0, 0.0, 0.0)):
+    """Quadrature point measure of a smooth parametrised surface (the
+    extension closing Section 5: an exact parametrisation gives the transform
+    of the surface measure to double precision).  Returns (points[n,3],
+    weights[n]), u-major.
+
+    ellipsoid: x(theta, phi) = (a sin(theta) cos(phi), b sin(theta) sin(phi),
+        c cos(theta)); substituting u = cos(theta), dA = |x_theta x x_phi| /
+        sin(theta) du dphi; Gauss-Legendre in u, trapezoid in phi.
+    torus: x(u, v) = ((a + b cos v) cos u, (a + b cos v) sin u, b sin v);
+        dA = |x_u x x_v| du dv; trapezoid in both."""
+    c0 = np.asarray(center, dtype=np.float64)
+    if kind == "ellipsoid":
+        u, wu = gauss_legendre(n_u)
+        phi = 2.0 * math.pi * np.arange(n_v) / n_v
+        U, PH = np.meshgrid(u, phi, indexing="ij")
+        TH = np.arccos(U)
+        x = np.stack([a * np.sin(TH) * np.cos(PH), b * np.sin(TH) * np.sin(PH), c * np.cos(TH)], axis=-1)
+        x_th = np.stack([a * np.cos(TH) * np.cos(PH), b * np.cos(TH) * np.sin(PH), -c * np.sin(TH)], axis=-1)
+        x_ph = np.stack([-a * np.sin(TH) * np.sin(PH), b * np.sin(TH) * np.cos(PH), np.zeros_like(TH)], axis=-1)
+        jac = np.linalg.norm(np.cross(x_th, x_ph), axis=-1) / np.sin(TH)
+        w = wu[:, None] * (2.0 * math.pi / n_v) * jac
+    elif kind == "torus":
+        uu = 2.0 * math.pi * np.arange(n_u) / n_u
+        vv = 2.0 * math.pi * np.arange(n_v) / n_v
+        U, V = np.meshgrid(uu, vv, indexing="ij")
+        rho = a + b * np.cos(V)
+        x = np.stack([rho * np.cos(U), rho * np.sin(U), b * np.sin(V)], axis=-1)
+        x_u = np.stack([-rho * np.sin(U), rho * np.cos(U), np.zeros_like(U)], axis=-1)
+        x_v = np.stack([-b * np.sin(V) * np.cos(U), -b * np.sin(V) * np.sin(U), b * np.cos(V)], axis=-1)
+        w = (2.0 * math.pi / n_u) * (2.0 * math.pi / n_v) * np.linalg.norm(np.cross(x_u, x_v), axis=-1)
+    else:
+        raise ValueError(kind)
+    return x.reshape(-1, 3) + c0, w.ravel()
+
+
+def spheroid_area(a: float, c: float) -> float:
+    """Area of the spheroid with equatorial radius a and polar semi-axis c
+    (textbook closed forms, prolate and oblate)."""
+    if abs(c - a) < 1e-15 * a:
+        return 4.0 * math.pi * a * a
+    if c > a:
+        e = math.sqrt(1.0 - a * a / (c * c))
+        return 2.0 * math.pi * a * a * (1.0 + c / (a * e) * math.asin(e))
+    e = math.sqrt(1.0 - c * c / (a * a))
+    return 2.0 * math.pi * a * a * (1.0 + (1.0 - e * e) / e * math.atanh(e))
 
 
 # --------------------------------------------------------------------------

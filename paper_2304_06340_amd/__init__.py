@@ -7,8 +7,9 @@ reduction; its NUFFT fast path and adjoint) runs in the HIP kernels of
 ``include/hsd.h``.  Importing the package does not load the library; the
 first Context does, and fails loudly if it has not been built.
 """
-from .api import (Context, HsdError, Mesh, Params, Result, Rule, Server, Ticket, distance,
-                  distance_grad, transform, transform_rule)
+from .api import (Context, HsdError, Mesh, Params, PointMeasure, Result, Rule, Server, SurfaceMeasure, Ticket,
+                  distance, distance_grad, transform, transform_rule)
 
-__all__ = ["Context", "HsdError", "Mesh", "Params", "Result", "Rule", "Server", "Ticket",
+__all__ = ["Context", "HsdError", "Mesh", "Params", "PointMeasure", "Result", "Rule", "Server", "SurfaceMeasure",
+           "Ticket",
            "distance", "distance_grad", "transform", "transform_rule"]

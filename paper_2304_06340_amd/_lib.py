@@ -29,6 +29,14 @@ class RuleDesc(C.Structure):
                 ("xi_max", C.c_double), ("M", C.c_int32)]
 
 
+class SurfaceDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_u", C.c_int32), ("n_v", C.c_int32), ("a", C.c_double),
+                ("b", C.c_double), ("c", C.c_double), ("center", C.c_double * 3), ("reserved", C.c_int32 * 4)]
+
+
+SURFACE_ELLIPSOID, SURFACE_TORUS = 0, 1
+
+
 class Params(C.Structure):
     _fields_ = [("s", C.c_double), ("form", C.c_int32), ("method", C.c_int32),
                 ("taylor_tau", C.c_double), ("tri_rule", C.c_int32), ("nufft_tol", C.c_double),
@@ -70,6 +78,9 @@ SIGNATURES = {
     "hsd_finalize": (None, [C.c_void_p]),
     "hsd_create_mesh": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64,
                                     C.c_int32, C.POINTER(C.c_void_p)]),
+    "hsd_create_point_measure": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                                             C.POINTER(C.c_void_p)]),
+    "hsd_create_surface_measure": (C.c_int32, [C.c_void_p, C.POINTER(SurfaceDesc), C.POINTER(C.c_void_p)]),
     "hsd_mesh_num_triangles": (C.c_int64, [C.c_void_p]),
     "hsd_mesh_num_vertices": (C.c_int64, [C.c_void_p]),
     "hsd_mesh_destroy": (None, [C.c_void_p]),

@@ -170,6 +170,65 @@ class Mesh:
             pass
 
 
+class PointMeasure(Mesh):
+    """A weighted point measure sum_q c_q delta(x - y_q) (hsd_create_point_measure),
+    e.g. a quadrature of a smooth parametrised surface; usable wherever a Mesh
+    is (except as the differentiated measure of distance_grad).  points [n,3]
+    and weights [n] float64, numpy arrays or torch tensors (device tensors are
+    read in place)."""
+
+    def __init__(self, ctx: Context, points, weights):
+        self.ctx = ctx
+        lib = ctx._lib
+        h = C.c_void_p()
+        if _is_torch(points) and points.is_cuda:
+            import torch
+            x = points.detach().to(torch.float64).contiguous()
+            w = weights.detach().to(device=x.device, dtype=torch.float64).contiguous()
+            _check(lib.hsd_create_point_measure(ctx.handle, C.c_void_p(x.data_ptr()), C.c_void_p(w.data_ptr()),
+                                                x.shape[0], L.MEM_DEVICE, C.byref(h)))
+        else:
+            if _is_torch(points):
+                points = points.detach().cpu().numpy()
+            if _is_torch(weights):
+                weights = weights.detach().cpu().numpy()
+            x = _host_f64(points, 3)
+            w = _host_f64(weights).ravel()
+            if len(w) != len(x):
+                raise HsdError(L.HSD_EINVAL, f"{len(x)} points but {len(w)} weights")
+            _check(lib.hsd_create_point_measure(ctx.handle, x.ctypes.data_as(C.c_void_p),
+                                                w.ctypes.data_as(C.c_void_p), len(x), L.MEM_HOST, C.byref(h)))
+        self.handle = h
+
+
+class SurfaceMeasure(Mesh):
+    """A built-in smooth parametrised surface as a quadrature point measure
+    (hsd_create_surface_measure): ``SurfaceMeasure.ellipsoid`` and
+    ``SurfaceMeasure.torus``."""
+
+    def __init__(self, ctx: Context, desc: L.SurfaceDesc):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(ctx._lib.hsd_create_surface_measure(ctx.handle, C.byref(desc), C.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def ellipsoid(cls, ctx, a=1.0, b=1.0, c=1.0, n_u=64, n_v=128, center=(0.0, 0.0, 0.0)):
+        d = L.SurfaceDesc()
+        d.kind, d.n_u, d.n_v = L.SURFACE_ELLIPSOID, int(n_u), int(n_v)
+        d.a, d.b, d.c = float(a), float(b), float(c)
+        d.center[:] = [float(x) for x in center]
+        return cls(ctx, d)
+
+    @classmethod
+    def torus(cls, ctx, R=2.0, r=0.5, n_u=128, n_v=64, center=(0.0, 0.0, 0.0)):
+        d = L.SurfaceDesc()
+        d.kind, d.n_u, d.n_v = L.SURFACE_TORUS, int(n_u), int(n_v)
+        d.a, d.b = float(R), float(r)
+        d.center[:] = [float(x) for x in center]
+        return cls(ctx, d)
+
+
 class Rule:
     """A device-resident frequency quadrature (hsd_freq_rule)."""
 

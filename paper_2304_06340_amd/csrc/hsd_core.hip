@@ -439,7 +439,119 @@ hsd_status hsd_create_mesh(hsd_ctx *ctx, const double *verts, int64_t nv, const 
 {
     hsd_status stt;
     if ((stt = check_ctx(ctx)) != HSD_OK) return stt;
-    return create_mesh_on(ctx, ctx->stream, verts, nv, tris, nt, mem_kind, out);
+    return create_mesh_on(ctx, ctx->stream, verts, nv, tris, nt, mem_kind, out, nullptr);
+}
+
+} // extern "C"
+
+namespace hsd {
+
+// Quadrature of a built-in parametrised surface (see hsd_surface_desc).
+hsd_status surface_points(const hsd_surface_desc *d, std::vector<double> &pts, std::vector<double> &w)
+{
+    if (!d) { set_error("NULL surface description"); return HSD_EINVAL; }
+    const int nu = d->n_u, nv = d->n_v;
+    if (nu < 1 || nv < 1 || (int64_t)nu * nv > INT32_MAX / 3) {
+        set_error("surface quadrature sizes n_u=%d n_v=%d", nu, nv);
+        return HSD_EINVAL;
+    }
+    for (double v : {d->a, d->b, d->center[0], d->center[1], d->center[2]})
+        if (!std::isfinite(v)) { set_error("surface parameters must be finite"); return HSD_EINVAL; }
+    const double twopi = 2.0 * M_PI;
+    pts.assign((size_t)nu * nv * 3, 0.0);
+    w.assign((size_t)nu * nv, 0.0);
+    if (d->kind == HSD_SURFACE_ELLIPSOID) {
+        if (!(d->a > 0.0) || !(d->b > 0.0) || !(d->c > 0.0) || !std::isfinite(d->c)) {
+            set_error("ellipsoid semi-axes must be positive");
+            return HSD_EINVAL;
+        }
+        std::vector<double> x, wx;
+        gauss_legendre(nu, x, wx);
+        const double a = d->a, b = d->b, c = d->c, dphi = twopi / nv;
+        for (int i = 0; i < nu; ++i) {
+            const double u = x[(size_t)i], s2 = std::max(0.0, 1.0 - u * u), s = std::sqrt(s2);
+            for (int j = 0; j < nv; ++j) {
+                const double phi = dphi * j, cp = std::cos(phi), sp = std::sin(phi);
+                const size_t q = (size_t)i * nv + j;
+                pts[3 * q] = d->center[0] + a * s * cp;
+                pts[3 * q + 1] = d->center[1] + b * s * sp;
+                pts[3 * q + 2] = d->center[2] + c * u;
+                w[q] = wx[(size_t)i] * dphi *
+                       std::sqrt(b * b * c * c * s2 * cp * cp + a * a * c * c * s2 * sp * sp + a * a * b * b * u * u);
+            }
+        }
+    } else if (d->kind == HSD_SURFACE_TORUS) {
+        if (!(d->b > 0.0) || !(d->a > d->b)) {
+            set_error("torus radii must satisfy a > b > 0");
+            return HSD_EINVAL;
+        }
+        const double R = d->a, r = d->b, du = twopi / nu, dv = twopi / nv;
+        for (int i = 0; i < nu; ++i) {
+            const double cu = std::cos(du * i), su = std::sin(du * i);
+            for (int j = 0; j < nv; ++j) {
+                const double cv = std::cos(dv * j), sv = std::sin(dv * j);
+                const size_t q = (size_t)i * nv + j;
+                pts[3 * q] = d->center[0] + (R + r * cv) * cu;
+                pts[3 * q + 1] = d->center[1] + (R + r * cv) * su;
+                pts[3 * q + 2] = d->center[2] + r * sv;
+                w[q] = du * dv * r * (R + r * cv);
+            }
+        }
+    } else {
+        set_error("unknown surface kind %d", d->kind);
+        return HSD_EINVAL;
+    }
+    return HSD_OK;
+}
+
+} // namespace hsd
+
+extern "C" {
+
+hsd_status hsd_create_surface_measure(hsd_ctx *ctx, const hsd_surface_desc *d, hsd_mesh **out)
+{
+    hsd_status stt;
+    if ((stt = check_ctx(ctx)) != HSD_OK) return stt;
+    std::vector<double> pts, w;
+    if ((stt = surface_points(d, pts, w)) != HSD_OK) return stt;
+    return hsd_create_point_measure(ctx, pts.data(), w.data(), (int64_t)w.size(), HSD_MEM_HOST, out);
+}
+
+// Host test hook: the quadrature of a built-in surface (n_u * n_v points).
+int hsd__host_surface_points(const hsd_surface_desc *d, double *pts, double *w)
+{
+    std::vector<double> p, ww;
+    if (surface_points(d, p, ww) != HSD_OK) return -1;
+    std::memcpy(pts, p.data(), p.size() * 8);
+    std::memcpy(w, ww.data(), ww.size() * 8);
+    return 0;
+}
+
+hsd_status hsd_create_point_measure(hsd_ctx *ctx, const double *points, const double *weights, int64_t n,
+                                    int32_t mem_kind, hsd_mesh **out)
+{
+    hsd_status stt;
+    if ((stt = check_ctx(ctx)) != HSD_OK) return stt;
+    if (n < 0 || n > INT32_MAX / 3) { set_error("bad point count %lld", (long long)n); return HSD_EINVAL; }
+    if (n > 0 && (!points || !weights)) { set_error("NULL point arrays"); return HSD_EINVAL; }
+    std::vector<int32_t> tris((size_t)n * 3);
+    for (int64_t i = 0; i < n; ++i) tris[3 * i] = tris[3 * i + 1] = tris[3 * i + 2] = (int32_t)i;
+    // indices are host data whatever mem_kind says about points and weights:
+    // copy device points to the host first so that both arrays agree
+    std::vector<double> hp, hw;
+    const double *pp = points, *pw = weights;
+    if (mem_kind == HSD_MEM_DEVICE && n > 0) {
+        hp.resize((size_t)n * 3);
+        hw.resize((size_t)n);
+        HSD_HIP_TRY(hipMemcpy(hp.data(), points, (size_t)n * 24, hipMemcpyDeviceToHost));
+        HSD_HIP_TRY(hipMemcpy(hw.data(), weights, (size_t)n * 8, hipMemcpyDeviceToHost));
+        pp = hp.data();
+        pw = hw.data();
+    } else if (mem_kind != HSD_MEM_HOST && mem_kind != HSD_MEM_DEVICE) {
+        set_error("bad mem_kind %d", mem_kind);
+        return HSD_EINVAL;
+    }
+    return create_mesh_on(ctx, ctx->stream, pp, n, tris.data(), n, HSD_MEM_HOST, out, pw);
 }
 
 } // extern "C"
@@ -448,7 +560,8 @@ namespace hsd {
 
 // Mesh ingest on a given stream (the serving slots upload on their own).
 hsd_status create_mesh_on(hsd_ctx *ctx, hipStream_t st, const double *verts, int64_t nv,
-                          const int32_t *tris, int64_t nt, int32_t mem_kind, hsd_mesh **out)
+                          const int32_t *tris, int64_t nt, int32_t mem_kind, hsd_mesh **out,
+                          const double *point_weights)
 {
     hsd_status stt;
     if (!out) { set_error("out is NULL"); return HSD_EINVAL; }
@@ -492,6 +605,24 @@ hsd_status create_mesh_on(hsd_ctx *ctx, hipStream_t st, const double *verts, int
         }
     std::vector<TriRec> rec((size_t)nt);
     build_tri_records(m->host_verts.data(), m->host_tris.data(), nt, rec.data());
+    if (point_weights) {
+        // point measure: triangle t = (t, t, t) is the point y_t; its exact
+        // transform J e[z, z, z] = (J / 2) e^z, so J = 2 c_t gives c_t e^{-i xi.y_t}
+        std::vector<double> w((size_t)nt);
+        if (mem_kind == HSD_MEM_HOST) {
+            if (nt) std::memcpy(w.data(), point_weights, (size_t)nt * 8);
+        } else if (nt) {
+            HSD_HIP_TRY(hipMemcpy(w.data(), point_weights, (size_t)nt * 8, hipMemcpyDeviceToHost));
+        }
+        for (int64_t t = 0; t < nt; ++t) {
+            if (!std::isfinite(w[(size_t)t])) {
+                set_error("point weight %lld is not finite", (long long)t);
+                return HSD_EINVAL;
+            }
+            rec[(size_t)t].J = 2.0 * w[(size_t)t];
+        }
+        m->point_measure = true;
+    }
     // vertex -> (3 t + slot) CSR, entries in increasing triangle order
     std::vector<int32_t> ptr((size_t)nv + 1, 0), ent((size_t)nt * 3);
     for (int64_t i = 0; i < nt * 3; ++i) ptr[(size_t)m->host_tris[i] + 1]++;
@@ -723,6 +854,10 @@ hsd_status hsd_distance_grad(hsd_ctx *ctx, const hsd_mesh *mu, const hsd_mesh *n
     if ((stt = validate_params(p)) != HSD_OK) return stt;
     if (p->method != HSD_METHOD_DIRECT) {
         set_error("hsd_distance_grad supports the direct method only");
+        return HSD_EINVAL;
+    }
+    if (mu->point_measure) {
+        set_error("hsd_distance_grad: the differentiated measure must be a mesh, not a point measure");
         return HSD_EINVAL;
     }
     if (mem_kind != HSD_MEM_HOST && mem_kind != HSD_MEM_DEVICE) { set_error("bad mem_kind"); return HSD_EINVAL; }

@@ -108,6 +108,7 @@ struct hsd_mesh {
     hsd::DevBuf csr_ent;      // int32[3*nt]   entries: 3*t + slot
     std::vector<double> host_verts;
     std::vector<int32_t> host_tris;
+    bool point_measure = false;   // built by hsd_create_point_measure
     std::atomic<int> refs{1};
     ~hsd_mesh();
 };
@@ -183,8 +184,8 @@ hsd_status launch_direct_sp_range(hipStream_t st, const MeshPair &mp, const hsd_
 hsd_status launch_direct_gen_range(hipStream_t st, const MeshPair &mp, const double *nodes,
                                    int64_t n, int form, double tau, int K, int64_t i_begin,
                                    int64_t i_count, double2 *partial);
-hsd_status create_mesh_on(hsd_ctx *ctx, hipStream_t st, const double *verts, int64_t nv,
-                          const int32_t *tris, int64_t nt, int32_t mem_kind, hsd_mesh **out);
+hsd_status create_mesh_on(hsd_ctx *ctx, hipStream_t st, const double *verts, int64_t nv, const int32_t *tris,
+                          int64_t nt, int32_t mem_kind, hsd_mesh **out, const double *point_weights = nullptr);
 hsd_status launch_finalize(hipStream_t st, const hsd_rule *rule, const double *wtab,
                            const double *nutab, const double2 *partial, int K, int64_t n,
                            bool sphere_target, double2 *resid_out, double *block_out,

@@ -54,3 +54,32 @@ def test_struct_sizes_match_header():
     from paper_2304_06340_amd import _lib
     assert ctypes.sizeof(_lib.Params) == 88
     assert ctypes.sizeof(_lib.Result) == 48
+
+
+def test_struct_layouts_match_c_compiler(tmp_path):
+    """Every ctypes mirror against sizeof/offsetof from a C compiler reading
+    include/hsd.h itself."""
+    import shutil
+    import subprocess
+    from paper_2304_06340_amd import _lib
+    if not shutil.which("gcc"):
+        pytest.skip("no C compiler")
+    mirrors = {"hsd_params": _lib.Params, "hsd_result": _lib.Result, "hsd_rule_desc": _lib.RuleDesc,
+               "hsd_server_cfg": _lib.ServerCfg, "hsd_request": _lib.Request,
+               "hsd_request_times": _lib.RequestTimes, "hsd_surface_desc": _lib.SurfaceDesc}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hsd.h"', 'int main(void) {']
+    for cname, cls in mirrors.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, *_ in cls._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, *_ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
