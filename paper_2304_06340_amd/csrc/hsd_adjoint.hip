@@ -35,9 +35,9 @@ constexpr int kAdjNV = 10;   // S_E, V_0[3], V_1[3], V_2[3]
 constexpr double dsinc_coef(int k) { return ((k & 1) ? -1.0 : 1.0) * 2.0 * k * inv_factorial(2 * k + 1); }
 constexpr double dcosc_coef(int k) { return ((k & 1) ? 1.0 : -1.0) * (2.0 * k - 1.0) * inv_factorial(2 * k); }
 
-// d/dx sin(x)/x and d/dx (1-cos x)/x (x >= 0), with the series (k <= 8,
-// remainder < 1e-19) below 0.5.
-HSD_HD void dsinc_dcosc(double x, double sx, double cx, double &dsinc, double &dcosc)
+// d/dx sin(x)/x and d/dx (1-cos x)/x (x >= 0, ix = 1/x), with the series
+// (k <= 8, remainder < 1e-19) below 0.5.
+HSD_HD void dsinc_dcosc(double x, double ix, double sx, double cx, double &dsinc, double &dcosc)
 {
     if (x < 0.5) {
         const double x2 = x * x;
@@ -50,7 +50,6 @@ HSD_HD void dsinc_dcosc(double x, double sx, double cx, double &dsinc, double &d
         dsinc = ps * x;
         dcosc = pc;
     } else {
-        const double ix = 1.0 / x;
         const double sinc = sx * ix, cosc = (1.0 - cx) * ix;
         dsinc = (cx - sinc) * ix;
         dcosc = (sx - cosc) * ix;
@@ -85,28 +84,29 @@ HSD_HD void dd2_series_grad(double a, double b, double F[2], double Fa[2], doubl
     Fb[0] = br; Fb[1] = bi;
 }
 
-// One (triangle, node) pair: E = exp(-i theta_mid) F and the three
-// derivatives D_lo, D_mid, D_hi (complex, in the sorted frame).
-HSD_HD void pair_grad(double thmid, double a, double b, double tau, double E[2], double Dlo[2],
-                      double Dmid[2], double Dhi[2])
+// One (triangle, node) pair from its phases: hu = exp(-i a/2), hv =
+// exp(-i b/2), e1 = exp(-i theta_mid) as (cos, sin) pairs; ia, ib, iG are
+// 1/a, 1/b, 1/(a+b) (used only where a, b > 0 and G >= tau).  Gives
+// E = exp(-i theta_mid) F and the derivatives D_lo, D_mid, D_hi (complex, in
+// the sorted frame).
+HSD_HD void pair_grad_ph(double a, double b, double tau, cs64 hu, cs64 hv, cs64 e1, double ia, double ib,
+                         double iG, double E[2], double Dlo[2], double Dmid[2], double Dhi[2])
 {
     double F[2], Fa[2], Fb[2];
     const double G = a + b;
     if (G < tau) {
         dd2_series_grad(a, b, F, Fa, Fb);
     } else {
-        const cs64 hu = sincos64(0.5 * a), hv = sincos64(0.5 * b);
         const double sa = 2.0 * hu.s * hu.c, ca = hu.c * hu.c - hu.s * hu.s;
         const double sb = 2.0 * hv.s * hv.c, cb = hv.c * hv.c - hv.s * hv.s;
         // sinc and (1-cos)/x of a, b (limits at 0)
-        const double sinc_a = a > 0.0 ? sa / a : 1.0;
-        const double sinc_b = b > 0.0 ? sb / b : 1.0;
-        const double cosc_a = a > 0.0 ? 2.0 * hu.s * hu.s / a : 0.0;
-        const double cosc_b = b > 0.0 ? 2.0 * hv.s * hv.s / b : 0.0;
+        const double sinc_a = a > 0.0 ? sa * ia : 1.0;
+        const double sinc_b = b > 0.0 ? sb * ib : 1.0;
+        const double cosc_a = a > 0.0 ? 2.0 * hu.s * hu.s * ia : 0.0;
+        const double cosc_b = b > 0.0 ? 2.0 * hv.s * hv.s * ib : 0.0;
         double dsa, dca, dsb, dcb;
-        dsinc_dcosc(a, sa, ca, dsa, dca);
-        dsinc_dcosc(b, sb, cb, dsb, dcb);
-        const double iG = 1.0 / G;
+        dsinc_dcosc(a, ia, sa, ca, dsa, dca);
+        dsinc_dcosc(b, ib, sb, cb, dsb, dcb);
         F[0] = (cosc_b + cosc_a) * iG;
         F[1] = (sinc_b - sinc_a) * iG;
         Fa[0] = (dca - F[0]) * iG;
@@ -114,8 +114,7 @@ HSD_HD void pair_grad(double thmid, double a, double b, double tau, double E[2],
         Fb[0] = (dcb - F[0]) * iG;
         Fb[1] = (dsb - F[1]) * iG;
     }
-    const cs64 e1 = sincos64(thmid);   // exp(-i theta) = (c, -s)
-    const double er = e1.c, ei = -e1.s;
+    const double er = e1.c, ei = -e1.s;   // exp(-i theta) = (c, -s)
     E[0] = er * F[0] - ei * F[1];
     E[1] = er * F[1] + ei * F[0];
     Dlo[0] = -(er * Fa[0] - ei * Fa[1]);
@@ -125,6 +124,112 @@ HSD_HD void pair_grad(double thmid, double a, double b, double tau, double E[2],
     // -i E = (E_im, -E_re)
     Dmid[0] = E[1] - Dlo[0] - Dhi[0];
     Dmid[1] = -E[0] - Dlo[1] - Dhi[1];
+}
+
+HSD_HD void pair_grad(double thmid, double a, double b, double tau, double E[2], double Dlo[2],
+                      double Dmid[2], double Dhi[2])
+{
+    const double G = a + b;
+    pair_grad_ph(a, b, tau, sincos64(0.5 * a), sincos64(0.5 * b), sincos64(thmid), a > 0.0 ? 1.0 / a : 0.0,
+                 b > 0.0 ? 1.0 / b : 0.0, G > 0.0 ? 1.0 / G : 0.0, E, Dlo, Dmid, Dhi);
+}
+
+// Per-direction scatter of the three sorted-frame sums to the vertex slots.
+HSD_HD void adjoint_scatter(double nx, double ny, double nz, const double u[3], const int idx[3],
+                            double acc[kAdjNV])
+{
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const int j = idx[p];
+        // scatter by vertex index with selects (no dynamic register index)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) {
+            const double w = (j == jj) ? u[p] : 0.0;
+            acc[1 + 3 * jj] += w * nx;
+            acc[2 + 3 * jj] += w * ny;
+            acc[3 + 3 * jj] += w * nz;
+        }
+    }
+}
+
+// Lane body for spherical-product rules (radial nodes m_p +- h x_k of P
+// panels with n nodes each, r index = p n + j): the phases of the three
+// per-(triangle, direction) constants c (theta_mid, a/2, b/2) at radius
+// m_p +- h x_k are exp(-i m_p c) exp(-+i h x_k c), with the offsets' phases
+// computed once per direction and the panel centres stepped by
+// exp(-2 i h c); the nodes h - h x_k of panel 0 (small radius, where the
+// product would lose relative accuracy) are evaluated directly.  1/r comes
+// from a hardware reciprocal, 1/a and 1/b from per-direction reciprocals.
+HSD_HD void adjoint_lane_sp(const TriRec &T, const double *dirs, const double *radii, int P, int n, double h,
+                            const double *hx_tab, int64_t d_begin, int64_t d_end, const double2 *resid,
+                            const double *wdir, const double *wtab, double tau, double acc[kAdjNV])
+{
+    const int n_rad = P * n, nh = n / 2;
+    for (int i = 0; i < kAdjNV; ++i) acc[i] = 0.0;
+    for (int64_t d = d_begin; d < d_end; ++d) {
+        const double nx = dirs[3 * d], ny = dirs[3 * d + 1], nz = dirs[3 * d + 2];
+        const double t0 = nx * T.p0[0] + ny * T.p0[1] + nz * T.p0[2];
+        const double s1 = nx * T.e1[0] + ny * T.e1[1] + nz * T.e1[2];
+        const double s2 = nx * T.e2[0] + ny * T.e2[1] + nz * T.e2[2];
+        double v0 = 0.0, v1 = s1, v2 = s2;
+        int i0 = 0, i1 = 1, i2 = 2;
+        if (v1 < v0) { double t = v0; v0 = v1; v1 = t; int ti = i0; i0 = i1; i1 = ti; }
+        if (v2 < v1) { double t = v1; v1 = v2; v2 = t; int ti = i1; i1 = i2; i2 = ti; }
+        if (v1 < v0) { double t = v0; v0 = v1; v1 = t; int ti = i0; i0 = i1; i1 = ti; }
+        const double al = v1 - v0, be = v2 - v1, tmid = t0 + v1;
+        const double ial = al > 0.0 ? 1.0 / al : 0.0, ibe = be > 0.0 ? 1.0 / be : 0.0;
+        const double iGc = al + be > 0.0 ? 1.0 / (al + be) : 0.0;
+        const double wd = wdir[d];
+        const double fr[3] = {tmid, 0.5 * al, 0.5 * be};
+        cs64 step[3], c0[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            c0[c] = sincos64(h * fr[c]);
+            step[c] = pmul(c0[c], c0[c]);
+        }
+        double sE = 0.0, ulo = 0.0, umid = 0.0, uhi = 0.0;
+        for (int k = 0; k < nh; ++k) {
+            const double hx = hx_tab[k];
+            cs64 bk[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) bk[c] = sincos64(hx * fr[c]);
+            cs64 cp[3] = {c0[0], c0[1], c0[2]};
+            for (int p = 0; p < P; ++p) {
+                const double m = (double)(2 * p + 1) * h;
+#pragma unroll
+                for (int sg = 0; sg < 2; ++sg) {
+                    const double r = sg == 0 ? m + hx : m - hx;
+                    const int ir = p * n + (sg == 0 ? nh + k : nh - 1 - k);
+                    cs64 ph[3];
+                    if (sg == 1 && p == 0) {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) ph[c] = sincos64(r * fr[c]);
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) ph[c] = sg == 0 ? pmul(cp[c], bk[c]) : pmulc(cp[c], bk[c]);
+                    }
+                    const double irr = rcp64(r);
+                    const int64_t node = d * n_rad + ir;
+                    const double W = wd * wtab[ir];
+                    const double2 R = resid[node];
+                    const double qr = 2.0 * W * R.x, qi = -2.0 * W * R.y;
+                    double E[2], Dlo[2], Dmid[2], Dhi[2];
+                    pair_grad_ph(r * al, r * be, tau, ph[1], ph[2], ph[0], irr * ial, irr * ibe, irr * iGc, E, Dlo,
+                                 Dmid, Dhi);
+                    sE += qr * E[0] - qi * E[1];
+                    ulo += r * (qr * Dlo[0] - qi * Dlo[1]);
+                    umid += r * (qr * Dmid[0] - qi * Dmid[1]);
+                    uhi += r * (qr * Dhi[0] - qi * Dhi[1]);
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) cp[c] = pmul(cp[c], step[c]);
+            }
+        }
+        acc[0] += sE;
+        const double u[3] = {ulo, umid, uhi};
+        const int idx[3] = {i0, i1, i2};
+        adjoint_scatter(nx, ny, nz, u, idx, acc);
+    }
 }
 
 // Lane body: one triangle against directions [d_begin, d_end) x all radii.
@@ -164,18 +269,7 @@ HSD_HD void adjoint_lane(const TriRec &T, const double *dirs, const double *radi
         acc[0] += sE;
         const double u[3] = {ulo, umid, uhi};
         const int idx[3] = {i0, i1, i2};
-#pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            const int j = idx[p];
-            // scatter by vertex index with selects (no dynamic register index)
-#pragma unroll
-            for (int jj = 0; jj < 3; ++jj) {
-                const double w = (j == jj) ? u[p] : 0.0;
-                acc[1 + 3 * jj] += w * nx;
-                acc[2 + 3 * jj] += w * ny;
-                acc[3 + 3 * jj] += w * nz;
-            }
-        }
+        adjoint_scatter(nx, ny, nz, u, idx, acc);
     }
 }
 
@@ -184,7 +278,8 @@ __global__ __launch_bounds__(256) void k_adjoint(const TriRec *__restrict__ tris
                                                  const double *__restrict__ radii, int n_rad,
                                                  const double2 *__restrict__ resid,
                                                  const double *__restrict__ wdir,
-                                                 const double *__restrict__ wtab, double tau,
+                                                 const double *__restrict__ wtab, double tau, int P, int n,
+                                                 double h, const double *__restrict__ hx_tab,
                                                  double *__restrict__ part)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -193,7 +288,10 @@ __global__ __launch_bounds__(256) void k_adjoint(const TriRec *__restrict__ tris
     const int64_t d_end = n_dir * (blockIdx.y + 1) / S;
     const TriRec T = tris[t < nt ? t : 0];
     double acc[kAdjNV];
-    adjoint_lane(T, dirs, radii, n_rad, d_begin, d_end, resid, wdir, wtab, tau, acc);
+    if (hx_tab)   // spherical-product rule: radial product structure
+        adjoint_lane_sp(T, dirs, radii, P, n, h, hx_tab, d_begin, d_end, resid, wdir, wtab, tau, acc);
+    else
+        adjoint_lane(T, dirs, radii, n_rad, d_begin, d_end, resid, wdir, wtab, tau, acc);
     if (t >= nt) return;
     double *o = part + ((int64_t)blockIdx.y * nt + t) * kAdjNV;
 #pragma unroll
@@ -257,12 +355,17 @@ int adjoint_splits(int64_t nt, int64_t n_dir, int num_cu)
 
 hsd_status launch_adjoint_raw(hipStream_t st, const TriRec *tris, int64_t nt, const double *dirs, int64_t n_dir,
                               const double *radii, int n_rad, const double2 *resid, const double *wdir,
-                              const double *wtab, double tau, int S, double *part, double *tri_grad)
+                              const double *wtab, double tau, int S, double *part, double *tri_grad, int P, int n,
+                              double h, const double *hx_tab)
 {
     if (nt == 0) return HSD_OK;
+    if (hx_tab && (P <= 0 || n <= 0 || n % 2 || P * n != n_rad || !wdir)) {
+        set_error("adjoint: inconsistent spherical-product description");
+        return HSD_EINVAL;
+    }
     const int64_t blocks = (nt + 255) / 256;
     hipLaunchKernelGGL(k_adjoint, dim3((unsigned)blocks, (unsigned)S), dim3(256), 0, st, tris, nt, dirs, n_dir,
-                       radii, n_rad, resid, wdir, wtab, tau, part);
+                       radii, n_rad, resid, wdir, wtab, tau, P, n, h, hx_tab, part);
     HSD_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_adjoint_finish, dim3((unsigned)blocks), dim3(256), 0, st, tris, nt, S, part, tri_grad);
     HSD_HIP_TRY(hipGetLastError());
@@ -295,6 +398,22 @@ void hsd__host_adjoint_lane(const double *p0, const double *e1, const double *e2
     for (int c = 0; c < 3; ++c) { T.p0[c] = p0[c]; T.e1[c] = e1[c]; T.e2[c] = e2[c]; }
     T.J = J;
     adjoint_lane(T, dirs, radii, n_rad, 0, n_dir, (const double2 *)resid, nullptr, wtab, tau, acc);
+}
+
+// CPU run of both adjoint lane bodies for one triangle on a spherical-product
+// rule (self checks only): acc_sp from the radial product structure, acc_ref
+// from per-node sin/cos; resid [n_dir * P * n] complex, wdir [n_dir],
+// wtab [P * n] (radial), hx_tab [n / 2].
+void hsd__host_adjoint_lane_sp(const double *p0, const double *e1, const double *e2, double J, const double *dirs,
+                               int64_t n_dir, const double *radii, int P, int n, double h, const double *hx_tab,
+                               const double *resid, const double *wdir, const double *wtab, double tau,
+                               double *acc_sp, double *acc_ref)
+{
+    TriRec T;
+    for (int c = 0; c < 3; ++c) { T.p0[c] = p0[c]; T.e1[c] = e1[c]; T.e2[c] = e2[c]; }
+    T.J = J;
+    adjoint_lane_sp(T, dirs, radii, P, n, h, hx_tab, 0, n_dir, (const double2 *)resid, wdir, wtab, tau, acc_sp);
+    adjoint_lane(T, dirs, radii, P * n, 0, n_dir, (const double2 *)resid, wdir, wtab, tau, acc_ref);
 }
 
 void hsd__host_pair_grad(double thmid, double a, double b, double tau, double *out /*8*/)

@@ -886,8 +886,10 @@ hsd_status hsd_distance_grad(hsd_ctx *ctx, const hsd_mesh *mu, const hsd_mesh *n
     // the (2pi)^-3 w (1+r^2)^-s weights: SP -> wdir x radial table
     if ((stt = launch_adjoint_raw(st, mu->tris.as<const TriRec>(), mu->nt, dirs, n_dir,
                                   rule->d_radii.as<const double>(), n_rad, ctx->nodebuf.buf.as<const double2>(),
-                                  sp ? rule->d_wdir.as<const double>() : nullptr, wtab, p->taylor_tau, S,
-                                  ctx->partial.buf.as<double>(), tri_grad)) != HSD_OK)
+                                  sp ? rule->d_wdir.as<const double>() : nullptr, wtab,
+                                  std::max(p->taylor_tau, kAdjointTau), S,
+                                  ctx->partial.buf.as<double>(), tri_grad, sp ? rule->sp.P : 0, sp ? rule->sp.n : 0,
+                                  sp ? rule->sp.h : 0.0, sp ? rule->d_hx.as<const double>() : nullptr)) != HSD_OK)
         return stt;
     if ((stt = launch_gather(st, mu, tri_grad, vgrad)) != HSD_OK) return stt;
     HSD_HIP_TRY(hipEventRecord(ctx->ev1, st));

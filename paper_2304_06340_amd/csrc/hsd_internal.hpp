@@ -24,6 +24,11 @@ namespace hsd {
 // G = 0.25, the largest threshold accepted for this form).
 constexpr double kMixedTau = 0.1;
 
+// The adjoint's closed-branch derivatives (F_a, F_b) lose about eps / G^3 to
+// cancellation, 1e-10 at G = 1e-2; its series (twelve terms, truncation
+// below 1e-26 at G = 0.05) is therefore used up to G = kAdjointTau.
+constexpr double kAdjointTau = 0.05;
+
 // One triangle as the affine image p0 + [e1 e2] u of the standard simplex
 // (eq. def_affine_simplex) with its area ratio J = |e1 x e2| (gamma in eq.
 // simplex32_ft).  80 bytes, read by whole wavefronts at once (scalar loads).
@@ -205,10 +210,10 @@ int choose_k_splits_gen(int64_t n, int64_t nt, int num_cu, int req);
 
 // Adjoint (hsd_adjoint.hip).
 int adjoint_splits(int64_t nt, int64_t n_dir, int num_cu);
-hsd_status launch_adjoint_raw(hipStream_t st, const TriRec *tris, int64_t nt, const double *dirs,
-                              int64_t n_dir, const double *radii, int n_rad, const double2 *resid,
-                              const double *wdir, const double *wtab, double tau, int S,
-                              double *part /*[S][nt][10]*/, double *tri_grad /*[nt*9]*/);
+hsd_status launch_adjoint_raw(hipStream_t st, const TriRec *tris, int64_t nt, const double *dirs, int64_t n_dir,
+                              const double *radii, int n_rad, const double2 *resid, const double *wdir,
+                              const double *wtab, double tau, int S, double *part, double *tri_grad, int P = 0,
+                              int n = 0, double h = 0.0, const double *hx_tab = nullptr);
 hsd_status launch_gather(hipStream_t st, const hsd_mesh *m, const double *tri_grad,
                          double *grad);
 
