@@ -117,14 +117,18 @@ __global__ void k_gather_points(const double4 *__restrict__ pts, const int *__re
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(512) void k_spread(const double4 *__restrict__ spts, const int *__restrict__ offs,
                                                 int nbx, int n1, double h1, double half_w, double beta,
-                                                double *__restrict__ grid)
+                                                int nsplit, double *__restrict__ grid)
 {
     __shared__ double kv[kChunk][3 * kBin];
     __shared__ double cw[kChunk];
     __shared__ double gc[kChunk][3];
     __shared__ int nkeep;
     const int tx = threadIdx.x & 7, ty = (threadIdx.x >> 3) & 7, tz = threadIdx.x >> 6;
-    const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+    // grid.z = tile z index x point-list split: split s takes every nsplit-th
+    // chunk of the tile's neighbourhood and writes its own partial grid
+    const int bx = blockIdx.x, by = blockIdx.y, bz = (int)(blockIdx.z % (unsigned)nbx);
+    const int split = (int)(blockIdx.z / (unsigned)nbx);
+    int chunk_no = 0;
     const int org[3] = {bx * kBin, by * kBin, bz * kBin};
     const double half = 0.5 * n1;
     const double iw = 1.0 / half_w;
@@ -138,6 +142,7 @@ __global__ __launch_bounds__(512) void k_spread(const double4 *__restrict__ spts
                 const int nb = (nx * nbx + ny) * nbx + nz;
                 const int lo = offs[nb], hi = offs[nb + 1];
                 for (int c0 = lo; c0 < hi; c0 += kChunk) {
+                    if (chunk_no++ % nsplit != split) continue;   // block-uniform
                     const int cnt = (hi - c0) < kChunk ? (hi - c0) : kChunk;
                     if (threadIdx.x < kChunk) {
                         bool keep = false;
@@ -179,14 +184,15 @@ __global__ __launch_bounds__(512) void k_spread(const double4 *__restrict__ spts
                 }
             }
     const int lx = org[0] + tx, ly = org[1] + ty, lz = org[2] + tz;
-    if (lx < n1 && ly < n1 && lz < n1) grid[((int64_t)lx * n1 + ly) * n1 + lz] = acc;
+    if (lx < n1 && ly < n1 && lz < n1)
+        grid[(int64_t)split * n1 * n1 * n1 + ((int64_t)lx * n1 + ly) * n1 + lz] = acc;
 }
 
 // --------------------------------------------------------------------------
 // 3. pre-deconvolve + zero-pad into the fine grid (index m <-> l' = m or m - n2)
 // --------------------------------------------------------------------------
-__global__ void k_predeconv(const double *__restrict__ grid, int n1, const double *__restrict__ hinv, int n2,
-                            double2 *__restrict__ fine)
+__global__ void k_predeconv(const double *__restrict__ grid, int n1, int nsplit, const double *__restrict__ hinv,
+                            int n2, double2 *__restrict__ fine)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t tot = (int64_t)n2 * n2 * n2;
@@ -201,7 +207,11 @@ __global__ void k_predeconv(const double *__restrict__ grid, int n1, const doubl
         in = in && (l[d] >= 0 && l[d] < n1);
     }
     double v = 0.0;
-    if (in) v = grid[((int64_t)l[0] * n1 + l[1]) * n1 + l[2]] * hinv[l[0]] * hinv[l[1]] * hinv[l[2]];
+    if (in) {
+        const int64_t cell = ((int64_t)l[0] * n1 + l[1]) * n1 + l[2], n13 = (int64_t)n1 * n1 * n1;
+        for (int sp = 0; sp < nsplit; ++sp) v += grid[sp * n13 + cell];   // fixed order
+        v *= hinv[l[0]] * hinv[l[1]] * hinv[l[2]];
+    }
     fine[g] = make_double2(v, 0.0);
 }
 
@@ -496,7 +506,11 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
                                           st));
     if ((stt = ens(sc.sorttmp, sort_bytes)) != HSD_OK) return stt;
     if ((stt = ens(sc.offs, ((size_t)nbins + 1) * sizeof(int))) != HSD_OK) return stt;
-    if ((stt = ens(sc.grid1, (size_t)n1 * n1 * n1 * sizeof(double))) != HSD_OK) return stt;
+    // split each tile's point list over several blocks when the points are
+    // dense (a lattice rule squeezes a whole mesh into few bins): about one
+    // split per 2^21 points, at most 16
+    const int nsplit = (int)std::min<int64_t>(16, std::max<int64_t>(1, np >> 21));
+    if ((stt = ens(sc.grid1, (size_t)nsplit * n1 * n1 * n1 * sizeof(double))) != HSD_OK) return stt;
     if ((stt = ens(sc.fine, (size_t)n2 * n2 * n2 * sizeof(double2))) != HSD_OK) return stt;
     if (!sc.plan || sc.plan->n != n2) {
         sc.plan.reset(new FftPlan());
@@ -524,12 +538,12 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     hipLaunchKernelGGL(k_bin_offsets, dim3((unsigned)((np + 1 + 255) / 256)), dim3(256), 0, st,
                        sc.keys2.as<const int>(), np, nbins, sc.offs.as<int>());
     HSD_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_spread, dim3(nbx, nbx, nbx), dim3(512), 0, st, sc.spts.as<const double4>(),
-                       sc.offs.as<const int>(), nbx, n1, h1, 0.5 * w, beta, sc.grid1.as<double>());
+    hipLaunchKernelGGL(k_spread, dim3(nbx, nbx, nbx * nsplit), dim3(512), 0, st, sc.spts.as<const double4>(),
+                       sc.offs.as<const int>(), nbx, n1, h1, 0.5 * w, beta, nsplit, sc.grid1.as<double>());
     HSD_HIP_TRY(hipGetLastError());
     const int64_t tot2 = (int64_t)n2 * n2 * n2;
     hipLaunchKernelGGL(k_predeconv, dim3((unsigned)((tot2 + 255) / 256)), dim3(256), 0, st, sc.grid1.as<const double>(),
-                       n1, sc.hinv.as<const double>(), n2, sc.fine.as<double2>());
+                       n1, nsplit, sc.hinv.as<const double>(), n2, sc.fine.as<double2>());
     HSD_HIP_TRY(hipGetLastError());
     if ((stt = fft3d_forward(st, plan, sc.fine.as<double2>())) != HSD_OK) return stt;
     if (lattice) {

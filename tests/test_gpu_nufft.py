@@ -150,3 +150,26 @@ def test_nufft_paper_configuration(hsd_ctx, orc):
     empty.close()
     mesh.close()
     rule.close()
+
+
+def test_nufft_dense_points_split_spread(hsd_ctx, orc):
+    """5.2 million points (level 6 x 64-point GL rule) on a small lattice:
+    dense bins, so the spread splits each tile's point list over blocks and
+    sums the partial grids in fixed order.  Against the oracle's direct sum
+    at 64 seeded nodes, and bitwise repeatable."""
+    v, f = icosphere(6)
+    rule = hsd.Rule.cube_trapezoid(hsd_ctx, 10.0, 32)
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    p = hsd.Params(method="nufft3", tri_rule="gl8x8", nufft_tol=1e-10)
+    got = hsd.transform_rule(hsd_ctx, mesh, rule, p)
+    again = hsd.transform_rule(hsd_ctx, mesh, rule, p)
+    assert np.array_equal(got, again)
+    o = orc.cube_trapezoid_rule(10.0, 32)
+    idx = np.random.default_rng(8).choice(len(o.nodes), size=64, replace=False)
+    pts, c = orc.point_cloud(v, f, "gl8x8")
+    ref = orc.point_sum(pts, c, o.nodes[idx])
+    err = np.max(np.abs(got[idx] - ref)) / np.sum(np.abs(c))
+    print(f"dense lattice spread: {len(c)} points, max |err| / sum|c| = {err:.2e}")
+    assert err <= 1e-10
+    mesh.close()
+    rule.close()
