@@ -108,8 +108,8 @@ typedef struct {
     int32_t form;        /* HSD_FORM_*                                             */
     int32_t method;      /* HSD_METHOD_*                                           */
     double taylor_tau;   /* series branch when the phase spread G < tau (1e-2);
-                            FP64: (0, 0.05]; mixed: (0, 0.25], and the mixed
-                            form uses max(tau, 0.1)                            */
+                            FP64: (0, 0.05]; mixed: (0, 0.75], and the mixed
+                            form uses max(tau, 0.75) with a longer series      */
     int32_t tri_rule;    /* HSD_TRI_* (NUFFT3 only)                                */
     double nufft_tol;    /* requested NUFFT accuracy (sets the width if width==0)  */
     int32_t nufft_width; /* ES kernel width in grid points (0: from tol)           */

@@ -134,9 +134,10 @@ hsd_status validate_params(const hsd_params *p)
         set_error("unknown method %d", p->method);
         return HSD_EINVAL;
     }
-    // the series is summed through the ninth power: its truncation stays
-    // below FP64 rounding for G < 0.05 and below 1e-13 for G < 0.25
-    const double tau_max = p->form == HSD_FORM_MIXED ? 0.25 : 0.05;
+    // the FP64 series is summed through the ninth power (truncation below
+    // FP64 rounding for G < 0.05), the mixed form's through the 11th (below
+    // 5e-12 for G < 0.75)
+    const double tau_max = p->form == HSD_FORM_MIXED ? kMixedTau : 0.05;
     if (!(p->taylor_tau > 0.0) || p->taylor_tau > tau_max) {
         set_error("taylor_tau must be in (0, %g] for this form (got %g)", tau_max, p->taylor_tau);
         return HSD_EINVAL;
@@ -159,7 +160,7 @@ double stated_rel_err(const hsd_params *p, int64_t nt)
 {
     (void)nt;
     if (p->method == HSD_METHOD_NUFFT3) return std::max(p->nufft_tol, 1e-15) * 1e4;
-    return p->form == HSD_FORM_FP64 ? 1e-10 : 5e-6;
+    return p->form == HSD_FORM_FP64 ? 1e-10 : 5e-7;
 }
 
 // Per-s tables of a rule: SP -> radial W_r = w_r r^2 (1+r^2)^-s (2 pi)^-3 and

@@ -181,7 +181,6 @@ HSD_HD void sp_lane_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t 
             const float Ka = (float)(2.0 * rcp64(ac) * iG);   // without J: applied in FP64
             const float Kb = (float)(2.0 * rcp64(bc) * iG);
             const double r_thr = fmax(tau, kMixedTau) * iG;
-            const float acf = (float)ac, bcf = (float)bc;
             const double fr[3] = {tmid, 0.5 * ac, 0.5 * bc};
             cs32 Bk[3], S[3], Cp[3];
 #pragma unroll
@@ -210,11 +209,16 @@ HSD_HD void sp_lane_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t 
                     double scale = J;
                     const float r = rr[slot];
                     if ((double)r < r_thr) {
-                        dd2_series_dev(r * acf, r * bcf, Yr, Xr);
-                        // r^2 J stays in FP64: rounded to FP32 it would give
-                        // every triangle of equal area the same relative error
+                        // the series in FP64 (its coefficients would carry
+                        // the same FP32 rounding for every triangle)
                         const double m = (double)(2 * (p0 + pl) + 1) * h;
                         const double rd = sg == 0 ? m + hx : m - hx;
+                        double sre, sim;
+                        dd2_series_dev<kMixedSeriesN>(rd * ac, rd * bc, sre, sim);
+                        Yr = (float)sre;
+                        Xr = (float)sim;
+                        // r^2 J stays in FP64: rounded to FP32 it would give
+                        // every triangle of equal area the same relative error
                         half = 0.5f;
                         scale = rd * rd * J;
                     } else {
@@ -303,7 +307,10 @@ HSD_HD void gen_node_mixed(const TriRec *A, int64_t nA, const TriRec *B, int64_t
             const cs32 E1 = sincos32_acc(t0 + mid);
             float Yr, Xr, half = 0.0f;
             if (a + b < fmax(tau, kMixedTau)) {
-                dd2_series_dev((float)a, (float)b, Yr, Xr);
+                double sre, sim;
+                dd2_series_dev<kMixedSeriesN>(a, b, sre, sim);
+                Yr = (float)sre;
+                Xr = (float)sim;
                 half = 0.5f;
             } else {
                 const double ac = fmax(a, kGapFloor32), bc = fmax(b, kGapFloor32);

@@ -42,8 +42,10 @@ constexpr double kGapFloor32 = 1e-18;
 // Per-(triangle, direction) constants in LDS.  ce/co are the coefficients of
 // the divided-difference power series as a polynomial in the radius r:
 // Re = sum_m ce[m] r^(2m), Im = r sum_m co[m] r^(2m) (see series_coefs).
-struct Scal64 { double Ka, Kb, rthr, pad; double ce[5], co[5]; };   // ce, co carry the factor J
-struct Scal32 { double rthr, J; float Ka, Kb; float ce[5], co[5]; }; // Ka, Kb, ce, co without J
+constexpr int kNC64 = 5;                        // series through r^9 (FP64 form)
+constexpr int kNC32 = (kMixedSeriesN + 1) / 2;  // through r^kMixedSeriesN (mixed form)
+struct Scal64 { double Ka, Kb, rthr, pad; double ce[kNC64], co[kNC64]; };   // ce, co carry the factor J
+struct Scal32 { double J; float rthr, Ka, Kb, pad; float ce[kNC32], co[kNC32]; }; // Ka, Kb, ce, co without J
 
 template <int PG> struct Batch64 {
     Scal64 sc[kTB];
@@ -84,15 +86,17 @@ HSD_HD TriDir tri_dir(const TriRec &T, double J, double nx, double ny, double nz
 // a power series in r for a = r ac, b = r bc:  sum_n (-i)^n r^n h_n with
 // h_n = H_n(ac, bc) / (n+2)!, H_n = sum_{m<=n} (-ac)^m bc^(n-m) (complete
 // homogeneous polynomial, by the recurrence H_n = bc H_{n-1} + (-ac)^n).
-// Split by parity: ce[m] = (-1)^m h_{2m}, co[m] = (-1)^(m+1) h_{2m+1}.
-// Through n = 9: the first omitted term is below 11 G^10 / 12! relative to
-// the leading 1/2, with G = r (ac + bc) the scaled phase spread.
-HSD_HD void series_coefs(double ac, double bc, double scale, double ce[5], double co[5])
+// Split by parity: ce[m] = (-1)^m h_{2m}, co[m] = (-1)^(m+1) h_{2m+1}, m < NC.
+// Through n = 2 NC - 1: the first omitted term is below
+// (2 NC + 1) G^(2 NC) / (2 NC + 2)! relative to the leading 1/2, with
+// G = r (ac + bc) the scaled phase spread.
+template <int NC>
+HSD_HD void series_coefs(double ac, double bc, double scale, double ce[NC], double co[NC])
 {
     double H = 1.0, pw = 1.0;
     ce[0] = 0.5 * scale;
 #pragma unroll
-    for (int n = 1; n <= 9; ++n) {
+    for (int n = 1; n <= 2 * NC - 1; ++n) {
         pw *= -ac;
         H = __builtin_fma(H, bc, pw);
         const double hn = H * inv_factorial(n + 2) * scale;
@@ -103,12 +107,12 @@ HSD_HD void series_coefs(double ac, double bc, double scale, double ce[5], doubl
 
 // Even/odd polynomial of the series at r (r2 = r^2): returns Re, Im / r.
 template <typename T>
-HSD_HD void series_eval(const T ce[5], const T co[5], T r2, T &pe, T &po)
+HSD_HD void series_eval(const T ce[kNC64], const T co[kNC64], T r2, T &pe, T &po)
 {
-    pe = ce[4];
-    po = co[4];
+    pe = ce[kNC64 - 1];
+    po = co[kNC64 - 1];
 #pragma unroll
-    for (int m = 3; m >= 0; --m) {
+    for (int m = kNC64 - 2; m >= 0; --m) {
         pe = pe * r2 + ce[m];
         po = po * r2 + co[m];
     }
@@ -142,18 +146,18 @@ HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, i
         sc->Kb = 2.0 * td.J * rcp64(td.bc) * td.iG;
         sc->rthr = tau * td.iG;
         sc->pad = 0.0;
-        series_coefs(td.ac, td.bc, td.J, sc->ce, sc->co);
+        series_coefs<kNC64>(td.ac, td.bc, td.J, sc->ce, sc->co);
     }
 }
 
 // Consumer, FP64: one triangle into the lane's 2*PG slots (slot 2*pl + sg).
 template <int PG>
 HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 P0[3], const cs64 (*Cp)[3], double h,
-                      double hx, int pfirst, double *acc_re, double *acc_im)
+                      double hx, int pbase, double *acc_re, double *acc_im)
 {
 #pragma unroll
     for (int pl = 0; pl < PG; ++pl) {
-        const int p = pfirst + pl;
+        const int p = pbase + pl;
         const double m = (double)(2 * p + 1) * h;
 #pragma unroll
         for (int sg = 0; sg < 2; ++sg) {
@@ -162,7 +166,7 @@ HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 P0[3], cons
             cs64 E[3];
             // the small-radius node h - h x_k exists only in panel 0, which a
             // lane can hold only as its first panel
-            const bool direct = (sg == 1) && (pl == 0) && (pfirst == 0);
+            const bool direct = (sg == 1) && (pl == 0) && (pbase == 0);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const cs64 prod = sg == 0 ? pmul(Cp[pl][c], Bk[c]) : pmulc(Cp[pl][c], Bk[c]);
@@ -185,10 +189,12 @@ HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 P0[3], cons
     }
 }
 
-// Producer, mixed: FP32 phases from FP64-reduced angles.
+// Producer, mixed: FP32 phases from FP64-reduced angles.  Cp is the
+// triangle's whole row, indexed by panel offset in the wave; part j fills
+// panels j + kNH q.
 template <int PG>
 HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
-                      Scal32 *sc, cs32 Bk[3], cs32 P0[3], cs32 Cp[PG][3])
+                      Scal32 *sc, cs32 Bk[3], cs32 P0[3], cs32 (*Cp)[3])
 {
     const double fr[3] = {td.tmid, 0.5 * td.ac, 0.5 * td.bc};
     const double hx = hx_tab[j];
@@ -196,19 +202,24 @@ HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, i
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         Bk[c] = sincos32_acc(hx * fr[c]);
-        P0[c] = sincos32_acc(r0 * fr[c]);
+        // small-radius node of panel 0: its half-gap phases directly (they
+        // need relative accuracy); its theta_mid phase is formed by the
+        // consumer's product like every other node's
+        if (c > 0) P0[c] = sincos32_acc(r0 * fr[c]);
 #pragma unroll
-        for (int q = 0; q < PG; ++q) Cp[q][c] = sincos32_acc((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c]);
+        for (int q = 0; q < PG; ++q)
+            Cp[j + kNH * q][c] = sincos32_acc((double)(2 * (w0 + j + kNH * q) + 1) * h * fr[c]);
     }
     if (sc) {
         sc->Ka = (float)(2.0 * rcp64(td.ac) * td.iG);
         sc->Kb = (float)(2.0 * rcp64(td.bc) * td.iG);
-        sc->rthr = fmax(tau, kMixedTau) * td.iG;
+        sc->rthr = (float)(fmax(tau, kMixedTau) * td.iG);   // decides the branch only
+        sc->pad = 0.0f;
         sc->J = td.J;
-        double ce[5], co[5];
-        series_coefs(td.ac, td.bc, 1.0, ce, co);
+        double ce[kNC32], co[kNC32];
+        series_coefs<kNC32>(td.ac, td.bc, 1.0, ce, co);
 #pragma unroll
-        for (int m = 0; m < 5; ++m) {
+        for (int m = 0; m < kNC32; ++m) {
             sc->ce[m] = (float)ce[m];
             sc->co[m] = (float)co[m];
         }
@@ -219,55 +230,79 @@ HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, i
 // (closed branch) or r^2 J (series) is applied in FP64 as each contribution
 // is added to its FP64 running sum.  Rounding J or r^2 to FP32 would give
 // every triangle of equal area (most of a symmetric mesh) the same relative
-// error, which does not average out over the triangles.
+// error, which does not average out.
+//
+// Lane layout (mixed form): lane = (po, sg, k) = (lane / 16, lane / 8 % 2,
+// lane % 8) holds node m_p + h x_k (sg = 0) or m_p - h x_k (sg = 1) of the
+// panels p = w0 + po + 4 q, slot q < 2 PG.  A slot of the wave then covers a
+// quarter of the wave's radial range, so that the series threshold r G = tau
+// splits one slot per triangle and the others take one branch only.  The
+// half-gap phases are formed only where some lane takes the closed branch.
 template <int PG>
-HSD_HD void consume32(const Scal32 &sc, const cs32 Bk[3], const cs32 P0[3], const cs32 (*Cp)[3], double h,
-                      double hx, int pfirst, double *acc_re, double *acc_im)
+HSD_HD void consume32(const Scal32 &scr, const cs32 Bk[3], const cs32 P0[3], const cs32 (*Cp)[3],
+                      const float *rf, const float *r2f, const double *r2d, bool direct0,
+                      bool conj, double *acc_re, double *acc_im)
 {
+    constexpr int NS = 2 * PG;
+    const Scal32 sc = scr;   // one read of the triangle's constants per triangle
+    cs32 B[3];
 #pragma unroll
-    for (int pl = 0; pl < PG; ++pl) {
-        const int p = pfirst + pl;
-        const double m = (double)(2 * p + 1) * h;
+    for (int c = 0; c < 3; ++c) B[c] = cs32{Bk[c].c, conj ? -Bk[c].s : Bk[c].s};
 #pragma unroll
-        for (int sg = 0; sg < 2; ++sg) {
-            const int slot = 2 * pl + sg;
-            const double rd = sg == 0 ? m + hx : m - hx;
+    for (int q = 0; q < NS; ++q) {
+        const bool direct = q == 0 && direct0;   // the node h - h x_k of panel 0
+        const cs32 E0 = pmul(Cp[4 * q][0], B[0]);
+        float Yr, Xr, half;
+        double scale;
+        if (rf[q] < sc.rthr) {
+            // Re of the series minus its constant 1/2; the 1/2 term is added
+            // last, in one fused step with the rest of the product already
+            // summed, so that the rounding sees the exact total (1/2 rounded
+            // first and a sub-ulp rest added after it would err the same way
+            // for every triangle of a node).
+            const float r2 = r2f[q];
+            float pe = sc.ce[kNC32 - 1], po = sc.co[kNC32 - 1];
+#pragma unroll
+            for (int m = kNC32 - 2; m >= 1; --m) pe = __builtin_fmaf(pe, r2, sc.ce[m]);
+#pragma unroll
+            for (int m = kNC32 - 2; m >= 0; --m) po = __builtin_fmaf(po, r2, sc.co[m]);
+            Yr = pe * r2;
+            Xr = rf[q] * po;
+            half = 0.5f;
+            scale = r2d[q] * sc.J;
+        } else {
             cs32 E[3];
-            const bool direct = (sg == 1) && (pl == 0) && (pfirst == 0);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const cs32 prod = sg == 0 ? pmul(Cp[pl][c], Bk[c]) : pmulc(Cp[pl][c], Bk[c]);
+            for (int c = 1; c < 3; ++c) {
+                const cs32 prod = pmul(Cp[4 * q][c], B[c]);
                 E[c] = direct ? P0[c] : prod;
             }
             const float Pv = sc.Kb * E[2].s;
             const float Pu = sc.Ka * E[1].s;
-            float Yr = __builtin_fmaf(Pv, E[2].s, Pu * E[1].s);
-            float Xr = __builtin_fmaf(Pv, E[2].c, -Pu * E[1].c);
-            double scale = sc.J;
-            float half = 0.0f;
-            if (rd < sc.rthr) {
-                // Re of the series minus its constant 1/2; the 1/2 term is
-                // added last, in one fused step with the rest of the product
-                // already summed, so that the rounding sees the exact total
-                // (1/2 rounded first and a sub-ulp rest added after it would
-                // err the same way for every triangle of a node).
-                const double r2d = rd * rd;
-                const float r2 = (float)r2d;
-                float pe = sc.ce[4], po = sc.co[4];
-#pragma unroll
-                for (int q = 3; q >= 1; --q) pe = __builtin_fmaf(pe, r2, sc.ce[q]);
-#pragma unroll
-                for (int q = 3; q >= 0; --q) po = __builtin_fmaf(po, r2, sc.co[q]);
-                Yr = pe * r2;
-                Xr = (float)rd * po;
-                half = 0.5f;
-                scale = r2d * sc.J;
-            }
-            const float tre = __builtin_fmaf(half, E[0].c, __builtin_fmaf(E[0].c, Yr, E[0].s * Xr));
-            const float tim = __builtin_fmaf(-half, E[0].s, __builtin_fmaf(E[0].c, Xr, -E[0].s * Yr));
-            acc_re[slot] = __builtin_fma(scale, (double)tre, acc_re[slot]);
-            acc_im[slot] = __builtin_fma(scale, (double)tim, acc_im[slot]);
+            Yr = __builtin_fmaf(Pv, E[2].s, Pu * E[1].s);
+            Xr = __builtin_fmaf(Pv, E[2].c, -Pu * E[1].c);
+            half = 0.0f;
+            scale = sc.J;
         }
+        const float tre = __builtin_fmaf(half, E0.c, __builtin_fmaf(E0.c, Yr, E0.s * Xr));
+        const float tim = __builtin_fmaf(-half, E0.s, __builtin_fmaf(E0.c, Xr, -E0.s * Yr));
+        acc_re[q] = __builtin_fma(scale, (double)tre, acc_re[q]);
+        acc_im[q] = __builtin_fma(scale, (double)tim, acc_im[q]);
+    }
+}
+
+// Radii of a mixed-form lane's slots (panels w0 + po + 4 q, sign sg) in
+// FP64, FP32 and squared.
+template <int PG>
+HSD_HD void mixed_lane_radii(int w0, int po, int sg, double h, double hx, float *rf, float *r2f, double *r2d)
+{
+#pragma unroll
+    for (int q = 0; q < 2 * PG; ++q) {
+        const double m = (double)(2 * (w0 + po + 4 * q) + 1) * h;
+        const double rd = sg == 0 ? m + hx : m - hx;
+        rf[q] = (float)rd;
+        r2d[q] = rd * rd;
+        r2f[q] = (float)r2d[q];
     }
 }
 
@@ -320,7 +355,14 @@ __global__ __launch_bounds__(256) void k_direct_wave(
     const int k = lane & 7, g = lane >> 3;             // consumer roles
     const int pt = lane >> 3, pj = lane & 7;           // producer roles
     const double hx = hx_tab[k];
-    const int pfirst = w0 + g * PG;
+    // FP64 consumer slots (pl, sg) hold panel pbase + pl; mixed-form lanes
+    // are laid out as (po, sg, k), see consume32
+    const int pbase = w0 + g * PG;
+    const int po = lane >> 4, sgl = (lane >> 3) & 1;
+    double r2d[F64 ? 1 : NS];
+    float rf[F64 ? 1 : NS], r2f[F64 ? 1 : NS];
+    if constexpr (!F64) mixed_lane_radii<PG>(w0, po, sgl, h, hx, rf, r2f, r2d);
+    const bool direct0 = w0 == 0 && po == 0 && sgl == 1;
     auto &L = lds[w];
 
     const int64_t ntot = nA + nB;
@@ -346,14 +388,15 @@ __global__ __launch_bounds__(256) void k_direct_wave(
                               L.P0[pt][pj], &L.Cp[pt][pj * PG]);
             else
                 produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
-                              L.P0[pt][pj], &L.Cp[pt][pj * PG]);
+                              L.P0[pt][pj], L.Cp[pt]);
         }
         wave_lds_sync();
         for (int t = 0; t < nvalid; ++t) {
             if constexpr (F64)
-                consume64<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx, pfirst, acc_re, acc_im);
+                consume64<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx, pbase, acc_re, acc_im);
             else
-                consume32<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx, pfirst, acc_re, acc_im);
+                consume32<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][po], rf, r2f, r2d, direct0, sgl == 1,
+                              acc_re, acc_im);
         }
         wave_lds_sync();
         if (++nb == kTileBatches) {
@@ -372,17 +415,16 @@ __global__ __launch_bounds__(256) void k_direct_wave(
     if (!valid) return;
     double2 *out = partial + (int64_t)blockIdx.y * N + d * (int64_t)(P * 2 * kNH);
 #pragma unroll
-    for (int pl = 0; pl < PG; ++pl) {
-        const int p = pfirst + pl;
+    for (int slot = 0; slot < NS; ++slot) {
+        // slot -> (panel, sign): (pbase + slot / 2, slot % 2) in FP64,
+        // (w0 + po + 4 slot, sgl) in the mixed form
+        const int p = F64 ? pbase + slot / 2 : w0 + po + 4 * slot;
+        const int sg = F64 ? slot % 2 : sgl;
         const double m = (double)(2 * p + 1) * h;
-#pragma unroll
-        for (int sg = 0; sg < 2; ++sg) {
-            const int slot = 2 * pl + sg;
-            const double r = sg == 0 ? m + hx : m - hx;
-            const double inv = 1.0 / (r * r);
-            const int jn = sg == 0 ? kNH + k : kNH - 1 - k;
-            out[(int64_t)p * (2 * kNH) + jn] = make_double2(tot_re[slot] * inv, tot_im[slot] * inv);
-        }
+        const double r = sg == 0 ? m + hx : m - hx;
+        const double inv = 1.0 / (r * r);
+        const int jn = sg == 0 ? kNH + k : kNH - 1 - k;
+        out[(int64_t)p * (2 * kNH) + jn] = make_double2(tot_re[slot] * inv, tot_im[slot] * inv);
     }
 }
 
@@ -449,7 +491,6 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
         const int w0 = wi * kNH * PG;
         std::vector<double> tre(64 * NS, 0.0), tim(64 * NS, 0.0);
         std::vector<double> are(64 * NS, 0.0), aim(64 * NS, 0.0);
-        std::vector<float> fre(64 * NS, 0.0f), fim(64 * NS, 0.0f);
         int nb = 0;
         for (int64_t tb = 0; tb < nA; tb += kTB) {
             const int nvalid = (int)std::min<int64_t>(kTB, nA - tb);
@@ -465,20 +506,25 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
                 } else {
                     auto &L = b32[0];
                     produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
-                                  L.P0[pt][pj], &L.Cp[pt][pj * PG]);
+                                  L.P0[pt][pj], L.Cp[pt]);
                 }
             }
             for (int lane = 0; lane < 64; ++lane) {
                 const int k = lane & 7, g = lane >> 3;
+                const int pbase = w0 + g * PG;
+                const int po = lane >> 4, sgl = (lane >> 3) & 1;
+                double r2d[NS];
+                float rf[NS], r2f[NS];
+                mixed_lane_radii<PG>(w0, po, sgl, h, hx_tab[k], rf, r2f, r2d);
                 for (int t = 0; t < nvalid; ++t) {
                     if (F64) {
                         auto &L = b64[0];
-                        consume64<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx_tab[k], w0 + g * PG,
+                        consume64<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx_tab[k], pbase,
                                       &are[lane * NS], &aim[lane * NS]);
                     } else {
                         auto &L = b32[0];
-                        consume32<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx_tab[k], w0 + g * PG,
-                                      &are[lane * NS], &aim[lane * NS]);
+                        consume32<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][po], rf, r2f, r2d,
+                                      w0 == 0 && po == 0 && sgl == 1, sgl == 1, &are[lane * NS], &aim[lane * NS]);
                     }
                 }
             }
@@ -488,25 +534,25 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
                     tre[i] += are[i];
                     tim[i] += aim[i];
                     are[i] = aim[i] = 0.0;
-                    fre[i] = fim[i] = 0.0f;
                 }
             }
         }
         for (int lane = 0; lane < 64; ++lane) {
             const int k = lane & 7, g = lane >> 3;
-            for (int pl = 0; pl < PG; ++pl)
-                for (int sg = 0; sg < 2; ++sg) {
-                    const int i = lane * NS + 2 * pl + sg;
-                    const double re = tre[i] + are[i];
-                    const double im = tim[i] + aim[i];
-                    const int p = w0 + g * PG + pl;
-                    const double m = (double)(2 * p + 1) * h;
-                    const double r = sg == 0 ? m + hx_tab[k] : m - hx_tab[k];
-                    const int jn = sg == 0 ? kNH + k : kNH - 1 - k;
-                    const int64_t q = (int64_t)p * 16 + jn;
-                    out[2 * q] = re / (r * r);
-                    out[2 * q + 1] = im / (r * r);
-                }
+            const int po = lane >> 4, sgl = (lane >> 3) & 1;
+            for (int slot = 0; slot < NS; ++slot) {
+                const int i = lane * NS + slot;
+                const double re = tre[i] + are[i];
+                const double im = tim[i] + aim[i];
+                const int p = F64 ? w0 + g * PG + slot / 2 : w0 + po + 4 * slot;
+                const int sg = F64 ? slot % 2 : sgl;
+                const double m = (double)(2 * p + 1) * h;
+                const double r = sg == 0 ? m + hx_tab[k] : m - hx_tab[k];
+                const int jn = sg == 0 ? kNH + k : kNH - 1 - k;
+                const int64_t q = (int64_t)p * 16 + jn;
+                out[2 * q] = re / (r * r);
+                out[2 * q + 1] = im / (r * r);
+            }
         }
     }
 }

@@ -17,12 +17,15 @@
 namespace hsd {
 
 // The mixed form evaluates the closed branch of the triangle transform in
-// FP32, where the difference sinc b - sinc a cancels: the error is about
-// 2 eps32 / G relative to the triangle's term at phase spread G.  Below
-// G = max(taylor_tau, kMixedTau) it sums the power series instead (no
-// cancellation; terms past the ninth power are below 1e-13 relative at
-// G = 0.25, the largest threshold accepted for this form).
-constexpr double kMixedTau = 0.1;
+// FP32, where the difference sinc b - sinc a cancels: its rounding error
+// grows like eps32 / G relative to the triangle's term at phase spread G.
+// These errors are random across triangles, but d^2 is quadratic in mu^, so
+// their variance enters d^2 as a positive bias that does not average out.
+// Below G = kMixedTau the mixed form therefore sums the power series instead
+// (coefficients formed in FP64, no cancellation), through the power
+// kMixedSeriesN, whose truncation stays below 5e-12 relative at G = 0.75.
+constexpr double kMixedTau = 0.75;
+constexpr int kMixedSeriesN = 11;
 
 // The adjoint's closed-branch derivatives (F_a, F_b) lose about eps / G^3 to
 // cancellation, 1e-10 at G = 1e-2; its series (twelve terms, truncation

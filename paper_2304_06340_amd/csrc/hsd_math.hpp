@@ -230,9 +230,10 @@ HSD_HD void sort3(T x0, T x1, T x2, T &lo, T &mid, T &hi)
 
 // Power series of the second divided difference of exp at (i a, 0, -i b)
 // (a, b >= 0): sum_n (-i)^n H_n / (n+2)!, H_n = sum_{m<=n} (-a)^m b^(n-m),
-// summed through n = 9; the first omitted term is below 11 G^10 / 12! with
-// G = a + b (4e-27 at G = 0.01, 2e-11 at G = 0.5).
-template <typename T>
+// summed through n = N; the first omitted term is below
+// (N+2) G^(N+1) / (N+3)! with G = a + b (N = 9: 2e-21 at G = 0.05;
+// N = 11: 5e-12 at G = 0.75).
+template <int N = 9, typename T>
 HSD_HD void dd2_series_dev(T a, T b, T &re, T &im);
 
 template <typename T>
@@ -243,25 +244,28 @@ HSD_HD void dd2_series(T a, T b, T &re, T &im)
 }
 
 // The same series without its constant term 1/2 (re is Re - 1/2).  The
-// mixed form adds the 1/2 term last, fused with the already summed rest: at
-// the smallest radii the rest is below one FP32 ulp of 1/2, and adding it to
-// a rounded 1/2-term would err the same way for every triangle of a node.
-template <typename T>
+// mixed form adds the 1/2 term last, fused
+// with the already summed rest: at the smallest radii the rest is below one
+// FP32 ulp of 1/2, and adding it to a rounded 1/2-term would err the same way
+// for every triangle of a node.
+template <int N, typename T>
 HSD_HD void dd2_series_dev(T a, T b, T &re, T &im)
 {
     const T na = -a;
-    T pw = na;
-    T H = b + na;                       // H_1
-    T sre = (T)0.0;                     // n = 0 term (1/2) left out
-    T sim = -H * (T)inv_factorial(3);   // n = 1
-    pw *= na; H = H * b + pw; sre -= H * (T)inv_factorial(4);   // n = 2
-    pw *= na; H = H * b + pw; sim += H * (T)inv_factorial(5);   // n = 3
-    pw *= na; H = H * b + pw; sre += H * (T)inv_factorial(6);   // n = 4
-    pw *= na; H = H * b + pw; sim -= H * (T)inv_factorial(7);   // n = 5
-    pw *= na; H = H * b + pw; sre -= H * (T)inv_factorial(8);   // n = 6
-    pw *= na; H = H * b + pw; sim += H * (T)inv_factorial(9);   // n = 7
-    pw *= na; H = H * b + pw; sre += H * (T)inv_factorial(10);  // n = 8
-    pw *= na; H = H * b + pw; sim -= H * (T)inv_factorial(11);  // n = 9
+    T pw = (T)1.0, H = (T)1.0;
+    T sre = (T)0.0, sim = (T)0.0;       // n = 0 term (1/2) left out
+#pragma unroll
+    for (int n = 1; n <= N; ++n) {
+        pw *= na;
+        H = H * b + pw;                 // H_n
+        const T t = H * (T)inv_factorial(n + 2);
+        switch (n & 3) {                // times (-i)^n
+        case 1: sim -= t; break;
+        case 2: sre -= t; break;
+        case 3: sim += t; break;
+        default: sre += t; break;
+        }
+    }
     re = sre;
     im = sim;
 }
