@@ -82,6 +82,7 @@ struct Scratch {
 struct FftPlan;
 struct NufftScratch {
     DevBuf pts, spts, keys, keys2, iota, offs, perm, sorttmp, grid1, fine, tri, ftq, hinv;
+    DevBuf titems, tstart, itile, tilebuf, scantmp;   // spread work items per tile
     std::unique_ptr<FftPlan> plan;
     NufftScratch();
     ~NufftScratch();

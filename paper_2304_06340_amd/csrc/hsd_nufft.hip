@@ -29,6 +29,7 @@
 #include <vector>
 
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "hsd_fft.hpp"
 #include "hsd_internal.hpp"
@@ -37,6 +38,7 @@
 namespace hsd {
 
 constexpr int kBin = 8;            // grid cells per bin / spread tile edge
+static_assert(kBin == 8, "the spread kernel splits value indices by shifts");
 constexpr int kChunk = 64;         // points staged in LDS per spread step
 constexpr int kMaxW = 16;          // largest kernel width supported
 
@@ -109,31 +111,93 @@ __global__ void k_gather_points(const double4 *__restrict__ pts, const int *__re
 }
 
 // --------------------------------------------------------------------------
-// 2. spread (gather form): block = one 8x8x8 tile of grid points.  The
-//    points of the 27 bins around the tile are staged in chunks of 64 (one
-//    wavefront loads a chunk); only those whose kernel support reaches the
-//    tile are kept (ballot compaction, order preserved), so a point costs
-//    work only in the tiles it touches.  Sum order: bin, then point order.
+// 2. spread (gather form): one wavefront per work item of one 8x8x8 tile of
+//    grid points; lane (tx, ty) holds the tile's column of 8 z values in
+//    registers.  The points of the 27 bins around the tile are staged in
+//    chunks of 64; only those whose kernel support reaches the tile are kept
+//    (ballot compaction, order preserved), so a point costs work only in the
+//    tiles it touches.  Per kept point the wave evaluates the 24 kernel
+//    values psi(x), psi(y), c psi(z) of the tile into LDS; each lane then
+//    reads its two values psi(x) psi(y) and the column c psi(z) (the same
+//    for all lanes) and does 8 FMAs.
+//
+//    Work items: a tile whose neighbourhood holds more than kItemChunks
+//    chunks gets several items, item s taking the chunks numbered
+//    [s kItemChunks, (s + 1) kItemChunks) of the tile's sequence (bins in
+//    order, chunks of 64 points); each writes a partial tile, summed in item
+//    order by k_tile_reduce.  Clustered points (a whole mesh in a few bins, as on the
+//    cube lattice) then spread over many waves instead of a few long ones.
+//    Sum order per grid point: item, then bin, then point order.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(512) void k_spread(const double4 *__restrict__ spts, const int *__restrict__ offs,
-                                                int nbx, int n1, double h1, double half_w, double beta,
-                                                int nsplit, double *__restrict__ grid)
+constexpr int kItemChunks = 64;   // candidate chunks per work item (at most)
+
+__device__ __forceinline__ void tile_of(int t, int nbx, int &bx, int &by, int &bz)
 {
-    __shared__ double kv[kChunk][3 * kBin];
-    __shared__ double cw[kChunk];
+    bz = t % nbx;
+    by = (t / nbx) % nbx;
+    bx = t / (nbx * nbx);
+}
+
+// titems[t] = number of work items of tile t (>= 1); titems[ntiles] = 0
+__global__ void k_tile_items(const int *__restrict__ offs, int nbx, int *__restrict__ titems)
+{
+    const int ntiles = nbx * nbx * nbx;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > ntiles) return;
+    if (t == ntiles) { titems[t] = 0; return; }
+    int bx, by, bz;
+    tile_of(t, nbx, bx, by, bz);
+    int64_t chunks = 0;
+    for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int nx = bx + dx, ny = by + dy, nz = bz + dz;
+                if (nx < 0 || ny < 0 || nz < 0 || nx >= nbx || ny >= nbx || nz >= nbx) continue;
+                const int nb = (nx * nbx + ny) * nbx + nz;
+                chunks += (offs[nb + 1] - offs[nb] + kChunk - 1) / kChunk;
+            }
+    titems[t] = (int)(chunks > 0 ? (chunks + kItemChunks - 1) / kItemChunks : 1);
+}
+
+// itile[item] = its tile, for the items of every tile (tstart = exclusive scan)
+__global__ void k_item_map(const int *__restrict__ tstart, int ntiles, int *__restrict__ itile)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntiles) return;
+    for (int i = tstart[t]; i < tstart[t + 1]; ++i) itile[i] = t;
+}
+
+__global__ __launch_bounds__(64) void k_spread(const double4 *__restrict__ spts, const int *__restrict__ offs,
+                                               const int *__restrict__ tstart, const int *__restrict__ itile,
+                                               int nbx, int n1, double h1, double half_w, double beta,
+                                               double *__restrict__ grid, double *__restrict__ tilebuf)
+{
+    constexpr int kSub = 32;                    // kept points evaluated per pass
+    __shared__ double kxy[kSub][2 * kBin];      // psi at the tile's x and y lines
+    __shared__ double kzc[kSub][kBin];          // c psi at the tile's z line
     __shared__ double gc[kChunk][3];
-    __shared__ int nkeep;
-    const int tx = threadIdx.x & 7, ty = (threadIdx.x >> 3) & 7, tz = threadIdx.x >> 6;
-    // grid.z = tile z index x point-list split: split s takes every nsplit-th
-    // chunk of the tile's neighbourhood and writes its own partial grid
-    const int bx = blockIdx.x, by = blockIdx.y, bz = (int)(blockIdx.z % (unsigned)nbx);
-    const int split = (int)(blockIdx.z / (unsigned)nbx);
-    int chunk_no = 0;
+    __shared__ double cw[kChunk];
+    const int ntiles = nbx * nbx * nbx;
+    const int item = blockIdx.x;
+    if (item >= tstart[ntiles]) return;         // beyond the items of this call
+    const int tile = itile[item];
+    const int split = item - tstart[tile], nsplit = tstart[tile + 1] - tstart[tile];
+    const int lane = threadIdx.x;
+    const int tx = lane & 7, ty = lane >> 3;
+    int bx, by, bz;
+    tile_of(tile, nbx, bx, by, bz);
+    const int64_t cbeg = (int64_t)split * kItemChunks, cend = cbeg + kItemChunks;
+    int64_t chunk_no = 0;   // first chunk of the current bin in the tile's sequence
     const int org[3] = {bx * kBin, by * kBin, bz * kBin};
     const double half = 0.5 * n1;
+    const double ih1 = 1.0 / h1;
     const double iw = 1.0 / half_w;
-    const int lane = threadIdx.x & 63;
-    double acc = 0.0;
+    // this lane's first (point, value) slot of an evaluation pass: slot
+    // v = lane + 64 j holds point v / 24, value v % 24
+    const int p0 = lane / (3 * kBin), r0 = lane - p0 * (3 * kBin);
+    double acc[kBin];
+#pragma unroll
+    for (int z = 0; z < kBin; ++z) acc[z] = 0.0;
     for (int dx = -1; dx <= 1; ++dx)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dz = -1; dz <= 1; ++dz) {
@@ -141,57 +205,116 @@ __global__ __launch_bounds__(512) void k_spread(const double4 *__restrict__ spts
                 if (nx < 0 || ny < 0 || nz < 0 || nx >= nbx || ny >= nbx || nz >= nbx) continue;
                 const int nb = (nx * nbx + ny) * nbx + nz;
                 const int lo = offs[nb], hi = offs[nb + 1];
-                for (int c0 = lo; c0 < hi; c0 += kChunk) {
-                    if (chunk_no++ % nsplit != split) continue;   // block-uniform
+                const int nch = (hi - lo + kChunk - 1) / kChunk;
+                const int64_t j0 = cbeg > chunk_no ? cbeg - chunk_no : 0;
+                const int64_t j1 = cend - chunk_no < nch ? cend - chunk_no : nch;
+                chunk_no += nch;
+                for (int64_t jc = j0; jc < j1; ++jc) {            // block-uniform
+                    const int c0 = lo + (int)jc * kChunk;
                     const int cnt = (hi - c0) < kChunk ? (hi - c0) : kChunk;
-                    if (threadIdx.x < kChunk) {
-                        bool keep = false;
-                        double g[3] = {0.0, 0.0, 0.0}, wv = 0.0;
-                        if (lane < cnt) {
-                            const double4 p = spts[c0 + lane];
-                            g[0] = p.x / h1 + half;
-                            g[1] = p.y / h1 + half;
-                            g[2] = p.z / h1 + half;
-                            wv = p.w;
-                            keep = true;
-                            for (int d = 0; d < 3; ++d)
-                                keep = keep && g[d] > (double)org[d] - half_w - 1.0 &&
-                                       g[d] < (double)(org[d] + kBin - 1) + half_w + 1.0;
-                        }
-                        const unsigned long long m = __ballot(keep);
-                        if (keep) {
-                            const int pos = __popcll(m & ((1ull << lane) - 1ull));
-                            gc[pos][0] = g[0];
-                            gc[pos][1] = g[1];
-                            gc[pos][2] = g[2];
-                            cw[pos] = wv;
-                        }
-                        if (lane == 0) nkeep = __popcll(m);
+                    bool keep = false;
+                    double g[3] = {0.0, 0.0, 0.0}, wv = 0.0;
+                    if (lane < cnt) {
+                        const double4 p = spts[c0 + lane];
+                        g[0] = __builtin_fma(p.x, ih1, half);
+                        g[1] = __builtin_fma(p.y, ih1, half);
+                        g[2] = __builtin_fma(p.z, ih1, half);
+                        wv = p.w;
+                        keep = true;
+                        for (int d = 0; d < 3; ++d)
+                            keep = keep && g[d] > (double)org[d] - half_w - 1.0 &&
+                                   g[d] < (double)(org[d] + kBin - 1) + half_w + 1.0;
                     }
-                    __syncthreads();
-                    const int nk = nkeep;
-                    if (nk > 0) {
-                        for (int v = threadIdx.x; v < nk * 3 * kBin; v += 512) {
-                            const int p = v / (3 * kBin), r = v - p * (3 * kBin);
-                            const int d = r / kBin, i = r - d * kBin;
-                            kv[p][r] = es_eval(((double)(org[d] + i) - gc[p][d]) * iw, beta);
+                    const unsigned long long m = __ballot(keep);
+                    const int nk = __popcll(m);
+                    if (nk == 0) continue;                        // wave-uniform
+                    if (keep) {
+                        const int pos = __popcll(m & ((1ull << lane) - 1ull));
+                        gc[pos][0] = g[0];
+                        gc[pos][1] = g[1];
+                        gc[pos][2] = g[2];
+                        cw[pos] = wv;
+                    }
+                    for (int s0 = 0; s0 < nk; s0 += kSub) {
+                        const int ns = (nk - s0) < kSub ? (nk - s0) : kSub;
+                        __syncthreads();
+                        int p = p0, r = r0;
+                        for (int v = lane; v < ns * 3 * kBin; v += 64) {
+                            const int d = r >> 3, i = r & 7;      // kBin = 8
+                            const double e = es_eval(((double)(org[d] + i) - gc[s0 + p][d]) * iw, beta);
+                            if (d < 2) kxy[p][r] = e;
+                            else kzc[p][i] = e * cw[s0 + p];
+                            // v += 64 = 2 * 24 + 16
+                            p += 2;
+                            r += 16;
+                            if (r >= 3 * kBin) { r -= 3 * kBin; ++p; }
                         }
                         __syncthreads();
-                        for (int p = 0; p < nk; ++p)
-                            acc = __builtin_fma(cw[p] * kv[p][tx], kv[p][kBin + ty] * kv[p][2 * kBin + tz], acc);
+                        int q = 0;
+                        for (; q + 2 <= ns; q += 2) {
+                            const double a0 = kxy[q][tx] * kxy[q][kBin + ty];
+                            const double a1 = kxy[q + 1][tx] * kxy[q + 1][kBin + ty];
+                            double z0[kBin], z1[kBin];
+#pragma unroll
+                            for (int z = 0; z < kBin; ++z) { z0[z] = kzc[q][z]; z1[z] = kzc[q + 1][z]; }
+#pragma unroll
+                            for (int z = 0; z < kBin; ++z) acc[z] = __builtin_fma(a1, z1[z], __builtin_fma(a0, z0[z], acc[z]));
+                        }
+                        if (q < ns) {
+                            const double a0 = kxy[q][tx] * kxy[q][kBin + ty];
+#pragma unroll
+                            for (int z = 0; z < kBin; ++z) acc[z] = __builtin_fma(a0, kzc[q][z], acc[z]);
+                        }
                     }
                     __syncthreads();
                 }
             }
-    const int lx = org[0] + tx, ly = org[1] + ty, lz = org[2] + tz;
-    if (lx < n1 && ly < n1 && lz < n1)
-        grid[(int64_t)split * n1 * n1 * n1 + ((int64_t)lx * n1 + ly) * n1 + lz] = acc;
+    if (nsplit > 1) {
+        double *dst = tilebuf + (int64_t)item * (kBin * kBin * kBin) + lane * kBin;
+#pragma unroll
+        for (int z = 0; z < kBin; ++z) dst[z] = acc[z];
+        return;
+    }
+    const int lx = org[0] + tx, ly = org[1] + ty;
+    if (lx < n1 && ly < n1) {
+        double *col = grid + ((int64_t)lx * n1 + ly) * n1;
+#pragma unroll
+        for (int z = 0; z < kBin; ++z)
+            if (org[2] + z < n1) col[org[2] + z] = acc[z];
+    }
+}
+
+// Sum of the partial tiles of tiles with several work items, in item order.
+__global__ __launch_bounds__(64) void k_tile_reduce(const double *__restrict__ tilebuf, const int *__restrict__ tstart,
+                                                    int nbx, int n1, double *__restrict__ grid)
+{
+    const int tile = blockIdx.x;
+    const int i0 = tstart[tile], i1 = tstart[tile + 1];
+    if (i1 - i0 <= 1) return;   // written by its only item
+    const int lane = threadIdx.x, tx = lane & 7, ty = lane >> 3;
+    double acc[kBin];
+#pragma unroll
+    for (int z = 0; z < kBin; ++z) acc[z] = 0.0;
+    for (int i = i0; i < i1; ++i) {
+        const double *src = tilebuf + (int64_t)i * (kBin * kBin * kBin) + lane * kBin;
+#pragma unroll
+        for (int z = 0; z < kBin; ++z) acc[z] += src[z];
+    }
+    int bx, by, bz;
+    tile_of(tile, nbx, bx, by, bz);
+    const int lx = bx * kBin + tx, ly = by * kBin + ty, z0 = bz * kBin;
+    if (lx < n1 && ly < n1) {
+        double *col = grid + ((int64_t)lx * n1 + ly) * n1;
+#pragma unroll
+        for (int z = 0; z < kBin; ++z)
+            if (z0 + z < n1) col[z0 + z] = acc[z];
+    }
 }
 
 // --------------------------------------------------------------------------
 // 3. pre-deconvolve + zero-pad into the fine grid (index m <-> l' = m or m - n2)
 // --------------------------------------------------------------------------
-__global__ void k_predeconv(const double *__restrict__ grid, int n1, int nsplit, const double *__restrict__ hinv,
+__global__ void k_predeconv(const double *__restrict__ grid, int n1, const double *__restrict__ hinv,
                             int n2, double2 *__restrict__ fine)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -208,9 +331,8 @@ __global__ void k_predeconv(const double *__restrict__ grid, int n1, int nsplit,
     }
     double v = 0.0;
     if (in) {
-        const int64_t cell = ((int64_t)l[0] * n1 + l[1]) * n1 + l[2], n13 = (int64_t)n1 * n1 * n1;
-        for (int sp = 0; sp < nsplit; ++sp) v += grid[sp * n13 + cell];   // fixed order
-        v *= hinv[l[0]] * hinv[l[1]] * hinv[l[2]];
+        const int64_t cell = ((int64_t)l[0] * n1 + l[1]) * n1 + l[2];
+        v = grid[cell] * (hinv[l[0]] * hinv[l[1]] * hinv[l[2]]);
     }
     fine[g] = make_double2(v, 0.0);
 }
@@ -506,11 +628,25 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
                                           st));
     if ((stt = ens(sc.sorttmp, sort_bytes)) != HSD_OK) return stt;
     if ((stt = ens(sc.offs, ((size_t)nbins + 1) * sizeof(int))) != HSD_OK) return stt;
-    // split each tile's point list over several blocks when the points are
-    // dense (a lattice rule squeezes a whole mesh into few bins): about one
-    // split per 2^21 points, at most 16
-    const int nsplit = (int)std::min<int64_t>(16, std::max<int64_t>(1, np >> 21));
-    if ((stt = ens(sc.grid1, (size_t)nsplit * n1 * n1 * n1 * sizeof(double))) != HSD_OK) return stt;
+    // spread work items: at most ntiles + 27 (np / 64 + nbins) / kItemChunks
+    // (each tile scans 27 bins of ceil(count / 64) chunks), a bound known
+    // without reading anything back
+    const int ntiles = nbins;
+    const int64_t max_items =
+        ntiles + (27 * ((np + kChunk - 1) / kChunk + (int64_t)nbins) + kItemChunks - 1) / kItemChunks;
+    if (max_items > INT32_MAX) {
+        set_error("NUFFT: too many spread work items");
+        return HSD_EINVAL;
+    }
+    size_t scan_bytes = 0;
+    HSD_HIP_TRY(rocprim::exclusive_scan(nullptr, scan_bytes, sc.titems.as<const int>(), sc.tstart.as<int>(), 0,
+                                        (size_t)ntiles + 1, rocprim::plus<int>(), st));
+    if ((stt = ens(sc.scantmp, scan_bytes)) != HSD_OK) return stt;
+    if ((stt = ens(sc.titems, ((size_t)ntiles + 1) * sizeof(int))) != HSD_OK) return stt;
+    if ((stt = ens(sc.tstart, ((size_t)ntiles + 1) * sizeof(int))) != HSD_OK) return stt;
+    if ((stt = ens(sc.itile, (size_t)max_items * sizeof(int))) != HSD_OK) return stt;
+    if ((stt = ens(sc.tilebuf, (size_t)max_items * kBin * kBin * kBin * sizeof(double))) != HSD_OK) return stt;
+    if ((stt = ens(sc.grid1, (size_t)n1 * n1 * n1 * sizeof(double))) != HSD_OK) return stt;
     if ((stt = ens(sc.fine, (size_t)n2 * n2 * n2 * sizeof(double2))) != HSD_OK) return stt;
     if (!sc.plan || sc.plan->n != n2) {
         sc.plan.reset(new FftPlan());
@@ -538,12 +674,24 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     hipLaunchKernelGGL(k_bin_offsets, dim3((unsigned)((np + 1 + 255) / 256)), dim3(256), 0, st,
                        sc.keys2.as<const int>(), np, nbins, sc.offs.as<int>());
     HSD_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_spread, dim3(nbx, nbx, nbx * nsplit), dim3(512), 0, st, sc.spts.as<const double4>(),
-                       sc.offs.as<const int>(), nbx, n1, h1, 0.5 * w, beta, nsplit, sc.grid1.as<double>());
+    hipLaunchKernelGGL(k_tile_items, dim3((unsigned)((ntiles + 1 + 255) / 256)), dim3(256), 0, st,
+                       sc.offs.as<const int>(), nbx, sc.titems.as<int>());
+    HSD_HIP_TRY(hipGetLastError());
+    HSD_HIP_TRY(rocprim::exclusive_scan(sc.scantmp.ptr, scan_bytes, sc.titems.as<const int>(), sc.tstart.as<int>(), 0,
+                                        (size_t)ntiles + 1, rocprim::plus<int>(), st));
+    hipLaunchKernelGGL(k_item_map, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st,
+                       sc.tstart.as<const int>(), ntiles, sc.itile.as<int>());
+    HSD_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_spread, dim3((unsigned)max_items), dim3(64), 0, st, sc.spts.as<const double4>(),
+                       sc.offs.as<const int>(), sc.tstart.as<const int>(), sc.itile.as<const int>(), nbx, n1, h1,
+                       0.5 * w, beta, sc.grid1.as<double>(), sc.tilebuf.as<double>());
+    HSD_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)ntiles), dim3(64), 0, st, sc.tilebuf.as<const double>(),
+                       sc.tstart.as<const int>(), nbx, n1, sc.grid1.as<double>());
     HSD_HIP_TRY(hipGetLastError());
     const int64_t tot2 = (int64_t)n2 * n2 * n2;
     hipLaunchKernelGGL(k_predeconv, dim3((unsigned)((tot2 + 255) / 256)), dim3(256), 0, st, sc.grid1.as<const double>(),
-                       n1, nsplit, sc.hinv.as<const double>(), n2, sc.fine.as<double2>());
+                       n1, sc.hinv.as<const double>(), n2, sc.fine.as<double2>());
     HSD_HIP_TRY(hipGetLastError());
     if ((stt = fft3d_forward(st, plan, sc.fine.as<double2>())) != HSD_OK) return stt;
     if (lattice) {
