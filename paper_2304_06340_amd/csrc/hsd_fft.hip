@@ -95,17 +95,22 @@ __device__ void stockham_stage(double2 *buf, int n, int Bt, int Ns, const double
     __syncthreads();
 }
 
+// Index map of a pruned axis: compact index c < 2e covers m < e and
+// m >= n - e (gap = n - 2e); gap = 0 is the identity.
+__device__ __forceinline__ int64_t unprune(int64_t c, int e, int gap) { return c < e ? c : c + gap; }
+
 // Batched 1-D FFTs along one axis.  Line (o, i) element e lives at
-// data[o * so + i * si + e * se]; blockIdx.x covers Bt consecutive i for
-// one o = blockIdx.y.
+// data[o * so + i * si + e * se]; blockIdx.x covers Bt consecutive compact
+// inner indices for one compact outer index blockIdx.y, each mapped by
+// unprune (e_i, gap_i) and (e_o, gap_o).
 __global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *__restrict__ data, int n, int Bt, int64_t se,
                                                           int64_t si, int64_t so, int64_t n_inner,
                                                           const double2 *__restrict__ tw, const int *__restrict__ plan,
-                                                          int n_stages)
+                                                          int n_stages, int e_i, int gap_i, int e_o, int gap_o)
 {
     extern __shared__ double2 lds[];
     const int64_t i0 = (int64_t)blockIdx.x * Bt;
-    const int64_t o = blockIdx.y;
+    const int64_t o = unprune(blockIdx.y, e_o, gap_o);
     const int nl = (int)((n_inner - i0) < Bt ? (n_inner - i0) : Bt);
     double2 *base = data + o * so;
     const int total = nl * n;
@@ -114,7 +119,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *__restrict__ 
         int line, e;
         if (se == 1) { line = idx / n; e = idx - line * n; }
         else { e = idx / nl; line = idx - e * nl; }
-        lds[(size_t)line * n + e] = base[(i0 + line) * si + (int64_t)e * se];
+        lds[(size_t)line * n + e] = base[unprune(i0 + line, e_i, gap_i) * si + (int64_t)e * se];
     }
     __syncthreads();
     int Ns = 1;
@@ -130,7 +135,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *__restrict__ 
         int line, e;
         if (se == 1) { line = idx / n; e = idx - line * n; }
         else { e = idx / nl; line = idx - e * nl; }
-        base[(i0 + line) * si + (int64_t)e * se] = lds[(size_t)line * n + e];
+        base[unprune(i0 + line, e_i, gap_i) * si + (int64_t)e * se] = lds[(size_t)line * n + e];
     }
 }
 
@@ -180,33 +185,39 @@ static int lines_per_block(int n)
     return std::max(1, std::min(kFftMaxElems / n, 16));
 }
 
-hsd_status fft3d_forward(hipStream_t st, const FftPlan &p, double2 *data)
+hsd_status fft3d_forward(hipStream_t st, const FftPlan &p, double2 *data, int e_in, int e_out)
 {
     const int n = p.n;
-    const int64_t n2 = (int64_t)n * n;
     const int bt = lines_per_block(n);
     const size_t lds = (size_t)bt * n * sizeof(double2);
     const int ns = (int)p.stages.size();
-    // axis z (contiguous): lines are rows, inner index = row
+    struct Range { int cnt, e, gap; };   // compact count and unprune map of an axis
+    auto range = [n](int e) {
+        return (e > 0 && 2 * e < n) ? Range{2 * e, e, n - 2 * e} : Range{n, n, 0};
+    };
+    const Range in = range(e_in), out = range(e_out);
+    // axis z (contiguous): outer = x, inner = y, both where the input lives
     {
-        const int64_t n_inner = n2;
-        dim3 grid((unsigned)((n_inner + bt - 1) / bt), 1);
+        dim3 grid((unsigned)((in.cnt + bt - 1) / bt), (unsigned)in.cnt);
         hipLaunchKernelGGL(k_fft_axis, grid, dim3(kFftThreads), lds, st, data, n, bt, (int64_t)1, (int64_t)n,
-                           (int64_t)0, n_inner, p.tw.as<const double2>(), p.plan.as<const int>(), ns);
+                           (int64_t)n * n, (int64_t)in.cnt, p.tw.as<const double2>(), p.plan.as<const int>(), ns,
+                           in.e, in.gap, in.e, in.gap);
         HSD_HIP_TRY(hipGetLastError());
     }
-    // axis y: element stride n, inner = z (stride 1), outer = x (stride n^2)
+    // axis y: element stride n; inner = z (wanted outputs), outer = x (input)
     {
-        dim3 grid((unsigned)((n + bt - 1) / bt), (unsigned)n);
-        hipLaunchKernelGGL(k_fft_axis, grid, dim3(kFftThreads), lds, st, data, n, bt, (int64_t)n, (int64_t)1, n2,
-                           (int64_t)n, p.tw.as<const double2>(), p.plan.as<const int>(), ns);
+        dim3 grid((unsigned)((out.cnt + bt - 1) / bt), (unsigned)in.cnt);
+        hipLaunchKernelGGL(k_fft_axis, grid, dim3(kFftThreads), lds, st, data, n, bt, (int64_t)n, (int64_t)1,
+                           (int64_t)n * n, (int64_t)out.cnt, p.tw.as<const double2>(), p.plan.as<const int>(), ns,
+                           out.e, out.gap, in.e, in.gap);
         HSD_HIP_TRY(hipGetLastError());
     }
-    // axis x: element stride n^2, inner = z, outer = y (stride n)
+    // axis x: element stride n^2; inner = z, outer = y (wanted outputs)
     {
-        dim3 grid((unsigned)((n + bt - 1) / bt), (unsigned)n);
-        hipLaunchKernelGGL(k_fft_axis, grid, dim3(kFftThreads), lds, st, data, n, bt, n2, (int64_t)1, (int64_t)n,
-                           (int64_t)n, p.tw.as<const double2>(), p.plan.as<const int>(), ns);
+        dim3 grid((unsigned)((out.cnt + bt - 1) / bt), (unsigned)out.cnt);
+        hipLaunchKernelGGL(k_fft_axis, grid, dim3(kFftThreads), lds, st, data, n, bt, (int64_t)n * n, (int64_t)1,
+                           (int64_t)n, (int64_t)out.cnt, p.tw.as<const double2>(), p.plan.as<const int>(), ns,
+                           out.e, out.gap, out.e, out.gap);
         HSD_HIP_TRY(hipGetLastError());
     }
     return HSD_OK;
@@ -217,8 +228,10 @@ hsd_status fft3d_forward(hipStream_t st, const FftPlan &p, double2 *data)
 extern "C" {
 
 // Test hook (not part of the public ABI): forward 3-D FFT of a host cube
-// [n][n][n] of interleaved complex values, in place, on `ctx`'s device.
-int hsd__test_fft3d(hsd_ctx *ctx, double *host_data, int n)
+// [n][n][n] of interleaved complex values, in place, on `ctx`'s device;
+// e_in, e_out as for fft3d_forward (with e_out > 0 only outputs with y and z
+// in the wrapped centred cube of half-extent e_out are defined).
+int hsd__test_fft3d_pruned(hsd_ctx *ctx, double *host_data, int n, int e_in, int e_out)
 {
     using namespace hsd;
     if (!ctx || !host_data) return HSD_EINVAL;
@@ -229,10 +242,12 @@ int hsd__test_fft3d(hsd_ctx *ctx, double *host_data, int n)
     const size_t bytes = (size_t)n * n * n * sizeof(double2);
     if ((stt = buf.alloc(ctx, bytes)) != HSD_OK) return stt;
     HSD_HIP_TRY(hipMemcpy(buf.ptr, host_data, bytes, hipMemcpyHostToDevice));
-    if ((stt = fft3d_forward(nullptr, plan, buf.as<double2>())) != HSD_OK) return stt;
+    if ((stt = fft3d_forward(nullptr, plan, buf.as<double2>(), e_in, e_out)) != HSD_OK) return stt;
     HSD_HIP_TRY(hipDeviceSynchronize());
     HSD_HIP_TRY(hipMemcpy(host_data, buf.ptr, bytes, hipMemcpyDeviceToHost));
     return HSD_OK;
 }
+
+int hsd__test_fft3d(hsd_ctx *ctx, double *host_data, int n) { return hsd__test_fft3d_pruned(ctx, host_data, n, 0, 0); }
 
 } // extern "C"

@@ -693,7 +693,16 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     hipLaunchKernelGGL(k_predeconv, dim3((unsigned)((tot2 + 255) / 256)), dim3(256), 0, st, sc.grid1.as<const double>(),
                        n1, sc.hinv.as<const double>(), n2, sc.fine.as<double2>());
     HSD_HIP_TRY(hipGetLastError());
-    if ((stt = fft3d_forward(st, plan, sc.fine.as<double2>())) != HSD_OK) return stt;
+    // the spread grid is zero beyond |l - n1/2| > X / h1 + w / 2 (all points
+    // lie within X of the origin), so the fine grid is zero outside the
+    // wrapped indices m < e, m >= n2 - e: the FFT skips those lines
+    const int e_occ = std::min(n1 / 2, (int)std::floor(X / h1 + 0.5 * w) + 2);
+    // and only the indices the read-out touches are wanted: the lattice
+    // indices |k| <= M / 2, or the interpolation stencils around the scaled
+    // targets |u| <= S n2 h1 / (2 pi) (w points from ceil(u - w/2))
+    const int e_want = lattice ? rule->cube_M / 2 + 2
+                               : std::min(n2 / 2, (int)std::floor(S * n2 * h1 / (2.0 * kPi) + 0.5 * w) + 2);
+    if ((stt = fft3d_forward(st, plan, sc.fine.as<double2>(), e_occ, e_want)) != HSD_OK) return stt;
     if (lattice) {
         hipLaunchKernelGGL(k_lattice_out, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
                            sc.fine.as<const double2>(), n2, rule->d_nodes.as<const double>(), N, 1.0 / rule->cube_h,

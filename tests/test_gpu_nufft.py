@@ -29,6 +29,39 @@ def test_fft3d_against_numpy(hsd_ctx, n):
     assert err <= 5e-15 * math.log2(n ** 3), err
 
 
+@pytest.mark.parametrize("n,e_in,e_out", [(48, 10, 0), (81, 20, 30), (64, 31, 12), (54, 0, 9)])
+def test_fft3d_pruned_against_numpy(hsd_ctx, n, e_in, e_out):
+    """The pruned passes: input zero outside indices m < e_in or m >= n - e_in
+    of every axis (a zero-padded centred grid in wrapped order), outputs
+    wanted only where y and z lie in the same band of half-extent e_out;
+    those outputs equal the full transform's."""
+    L = hsd_ctx._lib
+    f = L.hsd__test_fft3d_pruned
+    f.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int]
+
+    def band(e):
+        m = np.zeros(n, bool)
+        if e <= 0 or 2 * e >= n:
+            m[:] = True
+        else:
+            m[:e] = True
+            m[n - e:] = True
+        return m
+
+    rng = np.random.default_rng(n + e_in)
+    x = rng.normal(size=(n, n, n)) + 1j * rng.normal(size=(n, n, n))
+    occ = band(e_in)
+    x *= occ[:, None, None] & occ[None, :, None] & occ[None, None, :]
+    buf = np.ascontiguousarray(np.stack([x.real, x.imag], axis=-1))
+    assert f(hsd_ctx.handle, buf.ctypes.data_as(C.POINTER(C.c_double)), n, e_in, e_out) == 0
+    got = buf[..., 0] + 1j * buf[..., 1]
+    ref = np.fft.fftn(x)
+    want = band(e_out)
+    sel = np.broadcast_to(want[None, :, None] & want[None, None, :], x.shape)
+    err = np.max(np.abs(got[sel] - ref[sel])) / np.max(np.abs(ref))
+    assert err <= 5e-15 * math.log2(n ** 3), err
+
+
 SPEC = dict(r_max=24.0, n_panels=3, n_per_panel=8, n_cos=12, n_phi=24)
 
 
