@@ -167,6 +167,7 @@ struct hsd_rule {
         int w = 0;
         double beta = 0.0, h1 = 0.0;
         hsd::DevBuf inv;
+        hsd::DevBuf order;   // nodes in Morton order of their grid position
     };
     std::vector<std::unique_ptr<NufftDeconv>> nufft_deconv;
     std::mutex mu;

@@ -340,15 +340,20 @@ __global__ void k_predeconv(const double *__restrict__ grid, int n1, const doubl
 // --------------------------------------------------------------------------
 // 4. interpolate at the targets and divide by Phi^
 // --------------------------------------------------------------------------
+// Thread t handles node order[t]: nodes sorted by the Morton code of their
+// grid cell, so that a wavefront's stencils overlap in a compact region
+// (along a ray, 64 consecutive radii would span tens of cells) and the
+// gathers hit the caches.
 template <int W>
 __global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine, int n2, const double *__restrict__ dirs,
                                                 const double *__restrict__ radii, int n_rad, int64_t N, double h1,
                                                 double beta, const double *__restrict__ phi_inv,
-                                                double2 *__restrict__ out)
+                                                const int *__restrict__ order, double2 *__restrict__ out)
 {
     constexpr int w = W;   // kernel width: compile-time so the gathers unroll
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= N) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N) return;
+    const int64_t k = order[t];
     const int64_t d = k / n_rad;
     const int ir = (int)(k - d * n_rad);
     const double r = radii[ir];
@@ -393,6 +398,37 @@ __global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine
     const double n2d = (double)n2;
     const double f = h1 * h1 * h1 / (n2d * n2d * n2d) * phi_inv[k];
     out[k] = make_double2(re * f, im * f);
+}
+
+// Morton key (10 bits per axis) of each node's cell of 2 grid points at the
+// grid scale n2 h1 / (2 pi), with its index, for the sort behind k_interp's
+// node order.
+__device__ __forceinline__ unsigned morton_spread10(unsigned v)
+{
+    v &= 1023u;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_node_keys(const double *__restrict__ dirs, const double *__restrict__ radii,
+                                                   int n_rad, int64_t N, double scale, int n2,
+                                                   unsigned *__restrict__ keys, int *__restrict__ idx)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= N) return;
+    const int64_t d = k / n_rad;
+    const double r = radii[k - d * n_rad];
+    unsigned key = 0;
+    for (int a = 0; a < 3; ++a) {
+        const double u = r * dirs[3 * d + a] * scale + 0.5 * n2;
+        const int c = (int)floor(u) >> 1;
+        key |= morton_spread10((unsigned)(c < 0 ? 0 : (c > 1023 ? 1023 : c))) << a;
+    }
+    keys[k] = key;
+    idx[k] = (int)k;
 }
 
 // 1 / Phi^(xi_k) per node, Phi^(xi) = prod_a (w h1 / 2) 2 sum_q wpsi_q
@@ -714,24 +750,51 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     const double *dirs = sp ? rule->d_dirs.as<const double>() : rule->d_nodes.as<const double>();
     const int n_rad = sp ? (int)rule->n_rad : 1;
     const double *phi_inv = nullptr;
+    const int *order = nullptr;
     {
         hsd_rule *rm = const_cast<hsd_rule *>(rule);
         std::lock_guard<std::mutex> lk(rm->mu);
         for (const auto &e : rm->nufft_deconv)
-            if (e->w == w && e->beta == beta && e->h1 == h1) phi_inv = e->inv.as<const double>();
+            if (e->w == w && e->beta == beta && e->h1 == h1) {
+                phi_inv = e->inv.as<const double>();
+                order = e->order.as<const int>();
+            }
         if (!phi_inv) {
+            if (N > INT32_MAX) {
+                set_error("NUFFT: too many nodes");
+                return HSD_EINVAL;
+            }
             std::unique_ptr<hsd_rule::NufftDeconv> e(new hsd_rule::NufftDeconv());
             e->w = w;
             e->beta = beta;
             e->h1 = h1;
+            const dim3 ng((unsigned)((N + 255) / 256)), nb(256);
             if ((stt = e->inv.alloc(ctx, (size_t)N * sizeof(double))) != HSD_OK) return stt;
-            hipLaunchKernelGGL(k_phi_inv, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, dirs,
-                               rule->d_radii.as<const double>(), n_rad, N, h1, w, sc.ftq.as<const double2>(),
-                               (int)ftq.size(), e->inv.as<double>());
+            hipLaunchKernelGGL(k_phi_inv, ng, nb, 0, st, dirs, rule->d_radii.as<const double>(), n_rad, N, h1, w,
+                               sc.ftq.as<const double2>(), (int)ftq.size(), e->inv.as<double>());
             HSD_HIP_TRY(hipGetLastError());
-            // complete before other streams (serving slots) may read it
+            // node order for the interpolation: Morton order of the cells at
+            // this call's grid scale (any order is correct; later calls with
+            // another fine-grid size reuse it)
+            DevBuf keys, keys2, idx, tmp;
+            if ((stt = keys.alloc(ctx, (size_t)N * sizeof(unsigned))) != HSD_OK) return stt;
+            if ((stt = keys2.alloc(ctx, (size_t)N * sizeof(unsigned))) != HSD_OK) return stt;
+            if ((stt = idx.alloc(ctx, (size_t)N * sizeof(int))) != HSD_OK) return stt;
+            if ((stt = e->order.alloc(ctx, (size_t)N * sizeof(int))) != HSD_OK) return stt;
+            hipLaunchKernelGGL(k_node_keys, ng, nb, 0, st, dirs, rule->d_radii.as<const double>(), n_rad, N,
+                               (double)n2 * h1 / (2.0 * kPi), n2, keys.as<unsigned>(), idx.as<int>());
+            HSD_HIP_TRY(hipGetLastError());
+            size_t tmp_bytes = 0;
+            HSD_HIP_TRY(rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys.as<unsigned>(), keys2.as<unsigned>(),
+                                                  idx.as<int>(), e->order.as<int>(), (unsigned int)N, 0, 30, st));
+            if ((stt = tmp.alloc(ctx, std::max<size_t>(tmp_bytes, 8))) != HSD_OK) return stt;
+            HSD_HIP_TRY(rocprim::radix_sort_pairs(tmp.ptr, tmp_bytes, keys.as<unsigned>(), keys2.as<unsigned>(),
+                                                  idx.as<int>(), e->order.as<int>(), (unsigned int)N, 0, 30, st));
+            // complete before other streams (serving slots) may read them and
+            // before the temporaries are freed
             HSD_HIP_TRY(hipStreamSynchronize(st));
             phi_inv = e->inv.as<const double>();
+            order = e->order.as<const int>();
             rm->nufft_deconv.push_back(std::move(e));
         }
     }
@@ -740,7 +803,7 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     const double *rr = rule->d_radii.as<const double>();
     switch (w) {
 #define HSD_INTERP_W(WW)                                                                                        \
-    case WW: hipLaunchKernelGGL(k_interp<WW>, ig, ib, 0, st, fg, n2, dirs, rr, n_rad, N, h1, beta, phi_inv, out); \
+    case WW: hipLaunchKernelGGL(k_interp<WW>, ig, ib, 0, st, fg, n2, dirs, rr, n_rad, N, h1, beta, phi_inv, order, out); \
         break;
         HSD_INTERP_W(2) HSD_INTERP_W(3) HSD_INTERP_W(4) HSD_INTERP_W(5) HSD_INTERP_W(6) HSD_INTERP_W(7)
         HSD_INTERP_W(8) HSD_INTERP_W(9) HSD_INTERP_W(10) HSD_INTERP_W(11) HSD_INTERP_W(12) HSD_INTERP_W(13)
