@@ -36,14 +36,15 @@ constexpr double dsinc_coef(int k) { return ((k & 1) ? -1.0 : 1.0) * 2.0 * k * i
 constexpr double dcosc_coef(int k) { return ((k & 1) ? 1.0 : -1.0) * (2.0 * k - 1.0) * inv_factorial(2 * k); }
 
 // d/dx sin(x)/x and d/dx (1-cos x)/x (x >= 0, ix = 1/x), with the series
-// (k <= 8, remainder < 1e-19) below 0.5.
+// (k <= 7, first omitted terms below 1e-16 relative to the leading x/3 and
+// 1/2) below 0.5.
 HSD_HD void dsinc_dcosc(double x, double ix, double sx, double cx, double &dsinc, double &dcosc)
 {
     if (x < 0.5) {
         const double x2 = x * x;
-        double ps = dsinc_coef(8), pc = dcosc_coef(8);
+        double ps = dsinc_coef(7), pc = dcosc_coef(7);
 #pragma unroll
-        for (int k = 7; k >= 1; --k) {
+        for (int k = 6; k >= 1; --k) {
             ps = __builtin_fma(ps, x2, dsinc_coef(k));
             pc = __builtin_fma(pc, x2, dcosc_coef(k));
         }
@@ -58,13 +59,15 @@ HSD_HD void dsinc_dcosc(double x, double ix, double sx, double cx, double &dsinc
 
 // F(a,b) = sum_n (-i)^n H_n/(n+2)! and its a- and b-derivatives, with
 // H_n = b H_{n-1} + (-a)^n, dH_n/da = b dH_{n-1}/da - n (-a)^{n-1},
-// dH_n/db = H_{n-1} + b dH_{n-1}/db.  Terms up to n = 12 (a + b < 0.05).
+// dH_n/db = H_{n-1} + b dH_{n-1}/db.  Terms up to n = 9: for a + b < 0.05
+// the first omitted ones are below 1e-17 relative (F: G^10 / 12!; F_a, F_b:
+// 10 G^9 / 12! against the leading 1/6).
 HSD_HD void dd2_series_grad(double a, double b, double F[2], double Fa[2], double Fb[2])
 {
     double H = 1.0, A = 0.0, B = 0.0, pw = 1.0;   // (-a)^n
     double fr = 0.5, fi = 0.0, ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
 #pragma unroll
-    for (int n = 1; n <= 12; ++n) {
+    for (int n = 1; n <= 9; ++n) {
         const double pw_prev = pw;
         pw *= -a;
         const double Hprev = H;
@@ -159,8 +162,9 @@ HSD_HD void adjoint_scatter(double nx, double ny, double nz, const double u[3], 
 // computed once per direction and the panel centres stepped by
 // exp(-2 i h c); the nodes h - h x_k of panel 0 (small radius, where the
 // product would lose relative accuracy) are evaluated directly.  1/r comes
-// from a hardware reciprocal, 1/a and 1/b from per-direction reciprocals.
-HSD_HD void adjoint_lane_sp(const TriRec &T, const double *dirs, const double *radii, int P, int n, double h,
+// from the rule's table of reciprocal radii (the same for all lanes), 1/a
+// and 1/b from per-direction reciprocals.
+HSD_HD void adjoint_lane_sp(const TriRec &T, const double *dirs, const double *iradii, int P, int n, double h,
                             const double *hx_tab, int64_t d_begin, int64_t d_end, const double2 *resid,
                             const double *wdir, const double *wtab, double tau, double acc[kAdjNV])
 {
@@ -208,7 +212,7 @@ HSD_HD void adjoint_lane_sp(const TriRec &T, const double *dirs, const double *r
 #pragma unroll
                         for (int c = 0; c < 3; ++c) ph[c] = sg == 0 ? pmul(cp[c], bk[c]) : pmulc(cp[c], bk[c]);
                     }
-                    const double irr = rcp64(r);
+                    const double irr = iradii[ir];
                     const int64_t node = d * n_rad + ir;
                     const double W = wd * wtab[ir];
                     const double2 R = resid[node];
@@ -280,7 +284,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const TriRec *__restrict__ tris
                                                  const double *__restrict__ wdir,
                                                  const double *__restrict__ wtab, double tau, int P, int n,
                                                  double h, const double *__restrict__ hx_tab,
-                                                 double *__restrict__ part)
+                                                 const double *__restrict__ iradii, double *__restrict__ part)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int S = gridDim.y;
@@ -289,7 +293,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const TriRec *__restrict__ tris
     const TriRec T = tris[t < nt ? t : 0];
     double acc[kAdjNV];
     if (hx_tab)   // spherical-product rule: radial product structure
-        adjoint_lane_sp(T, dirs, radii, P, n, h, hx_tab, d_begin, d_end, resid, wdir, wtab, tau, acc);
+        adjoint_lane_sp(T, dirs, iradii, P, n, h, hx_tab, d_begin, d_end, resid, wdir, wtab, tau, acc);
     else
         adjoint_lane(T, dirs, radii, n_rad, d_begin, d_end, resid, wdir, wtab, tau, acc);
     if (t >= nt) return;
@@ -356,16 +360,16 @@ int adjoint_splits(int64_t nt, int64_t n_dir, int num_cu)
 hsd_status launch_adjoint_raw(hipStream_t st, const TriRec *tris, int64_t nt, const double *dirs, int64_t n_dir,
                               const double *radii, int n_rad, const double2 *resid, const double *wdir,
                               const double *wtab, double tau, int S, double *part, double *tri_grad, int P, int n,
-                              double h, const double *hx_tab)
+                              double h, const double *hx_tab, const double *iradii)
 {
     if (nt == 0) return HSD_OK;
-    if (hx_tab && (P <= 0 || n <= 0 || n % 2 || P * n != n_rad || !wdir)) {
+    if (hx_tab && (P <= 0 || n <= 0 || n % 2 || P * n != n_rad || !wdir || !iradii)) {
         set_error("adjoint: inconsistent spherical-product description");
         return HSD_EINVAL;
     }
     const int64_t blocks = (nt + 255) / 256;
     hipLaunchKernelGGL(k_adjoint, dim3((unsigned)blocks, (unsigned)S), dim3(256), 0, st, tris, nt, dirs, n_dir,
-                       radii, n_rad, resid, wdir, wtab, tau, P, n, h, hx_tab, part);
+                       radii, n_rad, resid, wdir, wtab, tau, P, n, h, hx_tab, iradii, part);
     HSD_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_adjoint_finish, dim3((unsigned)blocks), dim3(256), 0, st, tris, nt, S, part, tri_grad);
     HSD_HIP_TRY(hipGetLastError());
@@ -412,7 +416,10 @@ void hsd__host_adjoint_lane_sp(const double *p0, const double *e1, const double 
     TriRec T;
     for (int c = 0; c < 3; ++c) { T.p0[c] = p0[c]; T.e1[c] = e1[c]; T.e2[c] = e2[c]; }
     T.J = J;
-    adjoint_lane_sp(T, dirs, radii, P, n, h, hx_tab, 0, n_dir, (const double2 *)resid, wdir, wtab, tau, acc_sp);
+    std::vector<double> iradii((size_t)P * n);
+    for (size_t i = 0; i < iradii.size(); ++i) iradii[i] = 1.0 / radii[i];
+    adjoint_lane_sp(T, dirs, iradii.data(), P, n, h, hx_tab, 0, n_dir, (const double2 *)resid, wdir, wtab, tau,
+                    acc_sp);
     adjoint_lane(T, dirs, radii, P * n, 0, n_dir, (const double2 *)resid, wdir, wtab, tau, acc_ref);
 }
 

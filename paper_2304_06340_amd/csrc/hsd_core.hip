@@ -361,6 +361,7 @@ hsd_rule::~hsd_rule()
     d_wdir.release();
     d_hx.release();
     d_radii.release();
+    d_iradii.release();
     d_nodes.release();
     tabs.clear();
     ctx_release(c);
@@ -725,6 +726,10 @@ hsd_status hsd_freq_rule(hsd_ctx *ctx, const hsd_rule_desc *d, hsd_rule **out)
         HSD_HIP_TRY(hipMemcpyAsync(r->d_hx.ptr, hx.data(), hx.size() * 8, hipMemcpyHostToDevice, st));
         if ((stt = r->d_radii.alloc(ctx, sp.radii.size() * 8)) != HSD_OK) return stt;
         HSD_HIP_TRY(hipMemcpyAsync(r->d_radii.ptr, sp.radii.data(), sp.radii.size() * 8, hipMemcpyHostToDevice, st));
+        std::vector<double> iradii(sp.radii.size());
+        for (size_t i = 0; i < iradii.size(); ++i) iradii[i] = 1.0 / sp.radii[i];
+        if ((stt = r->d_iradii.alloc(ctx, iradii.size() * 8)) != HSD_OK) return stt;
+        HSD_HIP_TRY(hipMemcpyAsync(r->d_iradii.ptr, iradii.data(), iradii.size() * 8, hipMemcpyHostToDevice, st));
         HSD_HIP_TRY(hipStreamSynchronize(st));
     } else if (d->kind == HSD_RULE_EXPLICIT || d->kind == HSD_RULE_CUBE_TRAPEZOID) {
         if (d->kind == HSD_RULE_EXPLICIT) {
@@ -890,7 +895,8 @@ hsd_status hsd_distance_grad(hsd_ctx *ctx, const hsd_mesh *mu, const hsd_mesh *n
                                   sp ? rule->d_wdir.as<const double>() : nullptr, wtab,
                                   std::max(p->taylor_tau, kAdjointTau), S,
                                   ctx->partial.buf.as<double>(), tri_grad, sp ? rule->sp.P : 0, sp ? rule->sp.n : 0,
-                                  sp ? rule->sp.h : 0.0, sp ? rule->d_hx.as<const double>() : nullptr)) != HSD_OK)
+                                  sp ? rule->sp.h : 0.0, sp ? rule->d_hx.as<const double>() : nullptr,
+                                  sp ? rule->d_iradii.as<const double>() : nullptr)) != HSD_OK)
         return stt;
     if ((stt = launch_gather(st, mu, tri_grad, vgrad)) != HSD_OK) return stt;
     HSD_HIP_TRY(hipEventRecord(ctx->ev1, st));

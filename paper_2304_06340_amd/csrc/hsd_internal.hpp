@@ -151,6 +151,7 @@ struct hsd_rule {
     hsd::DevBuf d_wdir;                       // SP: [n_dir]
     hsd::DevBuf d_hx;                         // SP: h*x for the positive half [n/2]
     hsd::DevBuf d_radii;                      // SP: radial nodes [n_rad]; others: {1.0}
+    hsd::DevBuf d_iradii;                     // SP: their reciprocals [n_rad]
     hsd::DevBuf d_nodes;                      // EXPLICIT/CUBE: [n*3]
     int32_t cube_M = 0;                       // CUBE: lattice indices -M/2..M/2 per axis
     double cube_h = 0.0;                      // CUBE: lattice spacing 2 xi_max / M
@@ -218,7 +219,8 @@ int adjoint_splits(int64_t nt, int64_t n_dir, int num_cu);
 hsd_status launch_adjoint_raw(hipStream_t st, const TriRec *tris, int64_t nt, const double *dirs, int64_t n_dir,
                               const double *radii, int n_rad, const double2 *resid, const double *wdir,
                               const double *wtab, double tau, int S, double *part, double *tri_grad, int P = 0,
-                              int n = 0, double h = 0.0, const double *hx_tab = nullptr);
+                              int n = 0, double h = 0.0, const double *hx_tab = nullptr,
+                              const double *iradii = nullptr);
 hsd_status launch_gather(hipStream_t st, const hsd_mesh *m, const double *tri_grad,
                          double *grad);
 
