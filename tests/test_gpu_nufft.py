@@ -106,6 +106,36 @@ def test_nufft_explicit_nodes_and_mesh_vs_mesh(hsd_ctx, orc):
     assert abs(res.d2 - d2_ref) <= 1e-7 * d2_ref
 
 
+@pytest.mark.parametrize("kind", ["ball", "lattice", "explicit"])
+def test_nufft_off_centre_mesh(hsd_ctx, orc, kind):
+    """A mesh away from the origin: the points fill one side of the grid, so
+    the spread's occupied tiles and the data inside the pruned FFT bands are
+    asymmetric.  Transform against the oracle's direct point sum, for the
+    type-3 (ball and explicit nodes) and type-1 (lattice) paths."""
+    rng = np.random.default_rng(11)
+    v, f = icosphere(2)
+    v = v * 0.6 + np.array([1.1, -0.4, 0.7])
+    if kind == "ball":
+        rule = hsd.Rule.spherical_product(hsd_ctx, **SPEC)
+        nodes = orc.spherical_product_rule(**SPEC).nodes
+    elif kind == "lattice":
+        rule = hsd.Rule.cube_trapezoid(hsd_ctx, 10.0, 24)
+        nodes = orc.cube_trapezoid_rule(10.0, 24).nodes
+    else:
+        nodes = rng.normal(size=(2000, 3)) * np.array([9.0, 2.0, 5.0])
+        rule = hsd.Rule.explicit(hsd_ctx, nodes, rng.uniform(0.1, 1.0, len(nodes)))
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    p = hsd.Params(method="nufft3", tri_rule="gl8x8", nufft_tol=1e-9)
+    got = hsd.transform_rule(hsd_ctx, mesh, rule, p)
+    pts, c = orc.point_cloud(v, f, "gl8x8")
+    ref = orc.point_sum(pts, c, nodes)
+    err = np.max(np.abs(got - ref)) / np.sum(np.abs(c))
+    print(f"off-centre mesh, {kind} rule: max |err| / sum|c| = {err:.2e}")
+    assert err <= 1e-9
+    mesh.close()
+    rule.close()
+
+
 def test_nufft_distance_model_error_and_determinism(hsd_ctx, orc):
     """d^2 from the NUFFT path vs (i) the same d^2 from the direct point sum
     (NUFFT error, pinned) and (ii) the exact-triangle d^2 (the point-rule
@@ -187,9 +217,9 @@ def test_nufft_paper_configuration(hsd_ctx, orc):
 
 def test_nufft_dense_points_split_spread(hsd_ctx, orc):
     """5.2 million points (level 6 x 64-point GL rule) on a small lattice:
-    dense bins, so the spread splits each tile's point list over blocks and
-    sums the partial grids in fixed order.  Against the oracle's direct sum
-    at 64 seeded nodes, and bitwise repeatable."""
+    dense bins, so the spread cuts each dense tile's point list into several
+    work items whose partial tiles are summed in item order.  Against the
+    oracle's direct sum at 64 seeded nodes, and bitwise repeatable."""
     v, f = icosphere(6)
     rule = hsd.Rule.cube_trapezoid(hsd_ctx, 10.0, 32)
     mesh = hsd.Mesh(hsd_ctx, v, f)
