@@ -594,11 +594,13 @@ hsd_status create_mesh_on(hsd_ctx *ctx, hipStream_t st, const double *verts, int
         if (nv) HSD_HIP_TRY(hipMemcpy(m->host_verts.data(), verts, (size_t)nv * 3 * 8, hipMemcpyDeviceToHost));
         if (nt) HSD_HIP_TRY(hipMemcpy(m->host_tris.data(), tris, (size_t)nt * 3 * 4, hipMemcpyDeviceToHost));
     }
-    for (int64_t i = 0; i < nv * 3; ++i)
+    for (int64_t i = 0; i < nv * 3; ++i) {
         if (!std::isfinite(m->host_verts[i])) {
             set_error("vertex %lld is not finite", (long long)(i / 3));
             return HSD_EINVAL;
         }
+        m->extent = std::max(m->extent, std::fabs(m->host_verts[i]));
+    }
     for (int64_t i = 0; i < nt * 3; ++i)
         if (m->host_tris[i] < 0 || m->host_tris[i] >= nv) {
             set_error("triangle %lld: vertex index %d outside [0, %lld)", (long long)(i / 3),
@@ -775,6 +777,7 @@ hsd_status hsd_freq_rule(hsd_ctx *ctx, const hsd_rule_desc *d, hsd_rule **out)
         for (int64_t i = 0; i < r->n_nodes; ++i) {
             const double *x = &r->host_nodes[3 * i];
             r->host_radii[i] = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+            r->extent = std::max({r->extent, std::fabs(x[0]), std::fabs(x[1]), std::fabs(x[2])});
         }
         if ((stt = r->d_nodes.alloc(ctx, r->host_nodes.size() * 8)) != HSD_OK) return stt;
         HSD_HIP_TRY(hipMemcpyAsync(r->d_nodes.ptr, r->host_nodes.data(), r->host_nodes.size() * 8, hipMemcpyHostToDevice, st));

@@ -117,6 +117,7 @@ struct hsd_mesh {
     hsd::DevBuf csr_ent;      // int32[3*nt]   entries: 3*t + slot
     std::vector<double> host_verts;
     std::vector<int32_t> host_tris;
+    double extent = 0.0;          // max |vertex coordinate|
     bool point_measure = false;   // built by hsd_create_point_measure
     std::atomic<int> refs{1};
     ~hsd_mesh();
@@ -147,6 +148,7 @@ struct hsd_rule {
     std::vector<double> host_nodes;           // [n*3] flattened (all kinds)
     std::vector<double> host_weights;         // [n]
     std::vector<double> host_radii;           // [n]
+    double extent = 0.0;                      // max |node coordinate|
     hsd::DevBuf d_dirs;                       // SP: [n_dir*3]
     hsd::DevBuf d_wdir;                       // SP: [n_dir]
     hsd::DevBuf d_hx;                         // SP: h*x for the positive half [n/2]

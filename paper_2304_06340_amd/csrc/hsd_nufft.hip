@@ -48,10 +48,39 @@ struct EsKernel {
     double half;                   // w / 2
 };
 
+// psi(z) = exp(beta (sqrt(1 - z^2) - 1)) on |z| < 1, 0 elsewhere.  On the
+// device, without branches or library calls: sqrt(a) from the hardware
+// reciprocal square root refined by one Goldschmidt step and one Newton
+// correction; exp(x) for x in [-beta, 0] by Cody-Waite reduction
+// x = n ln 2 + r (ln 2 split in two), |r| <= ln 2 / 2, the Taylor series of
+// e^r through r^11 (truncation below 7e-15 relative) and a scaling by 2^n.
+constexpr double kLog2E = 1.4426950408889634;     // RN(1 / ln 2)
+constexpr double kLn2Hi = 0.6931471805599453;     // RN(ln 2)
+constexpr double kLn2Lo = 2.3190468138462996e-17; // RN(ln 2 - kLn2Hi)
+
 HSD_HD double es_eval(double z, double beta)
 {
-    const double a = 1.0 - z * z;
-    return a > 0.0 ? exp(beta * (sqrt(a) - 1.0)) : 0.0;
+    const double a = __builtin_fma(-z, z, 1.0);
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double ac = a > 0.0 ? a : 1.0;   // keeps the arithmetic finite off the support
+    const double y = __builtin_amdgcn_rsq(ac);
+    double sq = ac * y, hy = 0.5 * y;
+    const double e = __builtin_fma(-sq, hy, 0.5);
+    sq = __builtin_fma(sq, e, sq);
+    hy = __builtin_fma(hy, e, hy);
+    sq = __builtin_fma(__builtin_fma(-sq, sq, ac), hy, sq);
+    const double x = beta * (sq - 1.0);
+    const double n = __builtin_rint(x * kLog2E);
+    double r = __builtin_fma(-n, kLn2Hi, x);
+    r = __builtin_fma(-n, kLn2Lo, r);
+    double pe = inv_factorial(11);
+#pragma unroll
+    for (int k = 10; k >= 0; --k) pe = __builtin_fma(pe, r, inv_factorial(k));
+    const double v = ldexp(pe, (int)n);
+    return a > 0.0 ? v : 0.0;
+#else
+    return a > 0.0 ? std::exp(beta * (std::sqrt(a) - 1.0)) : 0.0;
+#endif
 }
 
 // --------------------------------------------------------------------------
@@ -117,9 +146,9 @@ __global__ void k_gather_points(const double4 *__restrict__ pts, const int *__re
 //    chunks of 64; only those whose kernel support reaches the tile are kept
 //    (ballot compaction, order preserved), so a point costs work only in the
 //    tiles it touches.  Per kept point the wave evaluates the 24 kernel
-//    values psi(x), psi(y), c psi(z) of the tile into LDS; each lane then
-//    reads its two values psi(x) psi(y) and the column c psi(z) (the same
-//    for all lanes) and does 8 FMAs.
+//    values psi(x), psi(y), psi(z) of the tile into LDS; each lane then
+//    forms psi(x) c psi(y) and, with the column psi(z) (the same for all
+//    lanes), does 8 FMAs.
 //
 //    Work items: a tile whose neighbourhood holds more than kItemChunks
 //    chunks gets several items, item s taking the chunks numbered
@@ -173,9 +202,8 @@ __global__ __launch_bounds__(64) void k_spread(const double4 *__restrict__ spts,
                                                double *__restrict__ grid, double *__restrict__ tilebuf)
 {
     constexpr int kSub = 32;                    // kept points evaluated per pass
-    __shared__ double kxy[kSub][2 * kBin];      // psi at the tile's x and y lines
-    __shared__ double kzc[kSub][kBin];          // c psi at the tile's z line
-    __shared__ double gc[kChunk][3];
+    __shared__ double kv[kSub][3 * kBin];       // psi at the tile's x, y and z lines
+    __shared__ double gt[kChunk][3];            // (tile origin - point) / (w / 2) per axis
     __shared__ double cw[kChunk];
     const int ntiles = nbx * nbx * nbx;
     const int item = blockIdx.x;
@@ -230,9 +258,8 @@ __global__ __launch_bounds__(64) void k_spread(const double4 *__restrict__ spts,
                     if (nk == 0) continue;                        // wave-uniform
                     if (keep) {
                         const int pos = __popcll(m & ((1ull << lane) - 1ull));
-                        gc[pos][0] = g[0];
-                        gc[pos][1] = g[1];
-                        gc[pos][2] = g[2];
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) gt[pos][d] = ((double)org[d] - g[d]) * iw;
                         cw[pos] = wv;
                     }
                     for (int s0 = 0; s0 < nk; s0 += kSub) {
@@ -240,10 +267,9 @@ __global__ __launch_bounds__(64) void k_spread(const double4 *__restrict__ spts,
                         __syncthreads();
                         int p = p0, r = r0;
                         for (int v = lane; v < ns * 3 * kBin; v += 64) {
+                            // value r of point p: grid line i = r % 8 of axis d = r / 8
                             const int d = r >> 3, i = r & 7;      // kBin = 8
-                            const double e = es_eval(((double)(org[d] + i) - gc[s0 + p][d]) * iw, beta);
-                            if (d < 2) kxy[p][r] = e;
-                            else kzc[p][i] = e * cw[s0 + p];
+                            kv[p][r] = es_eval(__builtin_fma((double)i, iw, gt[s0 + p][d]), beta);
                             // v += 64 = 2 * 24 + 16
                             p += 2;
                             r += 16;
@@ -252,18 +278,18 @@ __global__ __launch_bounds__(64) void k_spread(const double4 *__restrict__ spts,
                         __syncthreads();
                         int q = 0;
                         for (; q + 2 <= ns; q += 2) {
-                            const double a0 = kxy[q][tx] * kxy[q][kBin + ty];
-                            const double a1 = kxy[q + 1][tx] * kxy[q + 1][kBin + ty];
+                            const double a0 = kv[q][tx] * cw[s0 + q] * kv[q][kBin + ty];
+                            const double a1 = kv[q + 1][tx] * cw[s0 + q + 1] * kv[q + 1][kBin + ty];
                             double z0[kBin], z1[kBin];
 #pragma unroll
-                            for (int z = 0; z < kBin; ++z) { z0[z] = kzc[q][z]; z1[z] = kzc[q + 1][z]; }
+                            for (int z = 0; z < kBin; ++z) { z0[z] = kv[q][2 * kBin + z]; z1[z] = kv[q + 1][2 * kBin + z]; }
 #pragma unroll
                             for (int z = 0; z < kBin; ++z) acc[z] = __builtin_fma(a1, z1[z], __builtin_fma(a0, z0[z], acc[z]));
                         }
                         if (q < ns) {
-                            const double a0 = kxy[q][tx] * kxy[q][kBin + ty];
+                            const double a0 = kv[q][tx] * cw[s0 + q] * kv[q][kBin + ty];
 #pragma unroll
-                            for (int z = 0; z < kBin; ++z) acc[z] = __builtin_fma(a0, kzc[q][z], acc[z]);
+                            for (int z = 0; z < kBin; ++z) acc[z] = __builtin_fma(a0, kv[q][2 * kBin + z], acc[z]);
                         }
                     }
                     __syncthreads();
@@ -574,20 +600,13 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     w = std::max(2, std::min(w, kMaxW));
     const double beta = 0.97 * kPi * (1.0 - 0.5 / sigma) * w;
     // extent of the sources and of the targets per dimension
+    // (both computed once, when the mesh and the rule were created)
     double X = 0.0;
-    for (const hsd_mesh *m : {mu, nu}) {
-        if (!m) continue;
-        for (double v : m->host_verts) X = std::max(X, std::fabs(v));
-    }
+    for (const hsd_mesh *m : {mu, nu})
+        if (m) X = std::max(X, m->extent);
     X = std::max(X, 1e-3);
-    double S = 0.0;
     const bool sp = rule->kind == HSD_RULE_SPHERICAL_PRODUCT;
-    if (sp) {
-        S = rule->sp.r_max;
-    } else {
-        for (double v : rule->host_nodes) S = std::max(S, std::fabs(v));
-    }
-    S = std::max(S, 1e-3);
+    const double S = std::max(sp ? rule->sp.r_max : rule->extent, 1e-3);
     // Lattice targets (cube trapezoid rule, xi = h_xi k): type 1.  The sources
     // scaled to t = h_xi x must lie inside (-pi, pi) with the kernel's support
     // on a grid of n >= sigma (M+1) points per axis; then one grid serves as
