@@ -164,13 +164,15 @@ struct hsd_rule {
         hsd::DevBuf nu;                       // sphere transform 4 pi sin r / r
     };
     std::map<std::pair<double, double>, std::unique_ptr<Tables>> tabs;   // by (s, freq_unit)
-    // per-node 1 / Phi^(xi_k) of the type-3 NUFFT, by (width, beta, h1): it
-    // depends on the rule and the kernel only, not on the mesh
+    // per-node 1 / Phi^(xi_k) of the type-3 NUFFT and the nodes' grouping by
+    // interpolation tile, by (width, beta, h1, fine-grid size)
     struct NufftDeconv {
-        int w = 0;
+        int w = 0, n2 = 0;
         double beta = 0.0, h1 = 0.0;
         hsd::DevBuf inv;
-        hsd::DevBuf order;   // nodes in Morton order of their grid position
+        hsd::DevBuf order;   // nodes grouped by interpolation tile
+        hsd::DevBuf items;   // int4 (tile, first, end, 0) work items over `order`
+        int nitems = 0;
     };
     std::vector<std::unique_ptr<NufftDeconv>> nufft_deconv;
     std::mutex mu;

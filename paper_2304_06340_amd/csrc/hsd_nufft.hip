@@ -366,95 +366,100 @@ __global__ void k_predeconv(const double *__restrict__ grid, int n1, const doubl
 // --------------------------------------------------------------------------
 // 4. interpolate at the targets and divide by Phi^
 // --------------------------------------------------------------------------
-// Thread t handles node order[t]: nodes sorted by the Morton code of their
-// grid cell, so that a wavefront's stencils overlap in a compact region
-// (along a ray, 64 consecutive radii would span tens of cells) and the
-// gathers hit the caches.
-template <int W>
-__global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine, int n2, const double *__restrict__ dirs,
-                                                const double *__restrict__ radii, int n_rad, int64_t N, double h1,
-                                                double beta, const double *__restrict__ phi_inv,
-                                                const int *__restrict__ order, double2 *__restrict__ out)
+// Targets are grouped by the tile of TS^3 grid points that holds the origin
+// of their stencil (per axis lo = ceil(u - w/2), u the target in grid units,
+// shifted by H = n2/2 + w to be non-negative); TS = 18 - w, so that the box
+// of (TS + w - 1)^3 = 17^3 grid values covering every stencil of a tile
+// fills 78.6 KB of LDS.  A block stages the box (periodic indices, rows along
+// z), then its threads interpolate the tile's targets from LDS.  Tiles with
+// many targets are cut into several work items, one block each.
+template <int W> constexpr int interp_tile() { return 18 - W > 2 ? 18 - W : 2; }
+
+__device__ __forceinline__ int wrap_index(int m, int n)
 {
-    constexpr int w = W;   // kernel width: compile-time so the gathers unroll
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N) return;
-    const int64_t k = order[t];
-    const int64_t d = k / n_rad;
-    const int ir = (int)(k - d * n_rad);
-    const double r = radii[ir];
-    const double xi[3] = {r * dirs[3 * d], r * dirs[3 * d + 1], r * dirs[3 * d + 2]};
-    const double half_w = 0.5 * w;
-    const double iw = 1.0 / half_w;
-    const double scale = (double)n2 * h1 / (2.0 * kPi);
-    double wt[3][W];
-    int base[3];
-    for (int a = 0; a < 3; ++a) {
-        const double u = xi[a] * scale;
-        const int lo = (int)ceil(u - half_w);
-        base[a] = lo;
-        for (int i = 0; i < w; ++i) wt[a][i] = es_eval(((double)(lo + i) - u) * iw, beta);
-    }
-    // periodic grid indices: wrap each axis' first index once, then step by
-    // one with wrap-around
-    int start[3];
-    for (int a = 0; a < 3; ++a) {
-        int b0 = base[a] % n2;
-        start[a] = b0 < 0 ? b0 + n2 : b0;
-    }
-    double re = 0.0, im = 0.0;
-    int mx = start[0];
-    for (int i = 0; i < w; ++i, mx = (mx + 1 == n2 ? 0 : mx + 1)) {
-        int my = start[1];
-        for (int j = 0; j < w; ++j, my = (my + 1 == n2 ? 0 : my + 1)) {
-            const double wxy = wt[0][i] * wt[1][j];
-            const double2 *row = fine + ((int64_t)mx * n2 + my) * n2;
-            double sre = 0.0, sim = 0.0;
-            int mz = start[2];
-#pragma unroll
-            for (int l = 0; l < w; ++l, mz = (mz + 1 == n2 ? 0 : mz + 1)) {
-                const double2 v = row[mz];
-                sre = __builtin_fma(v.x, wt[2][l], sre);
-                sim = __builtin_fma(v.y, wt[2][l], sim);
-            }
-            re = __builtin_fma(sre, wxy, re);
-            im = __builtin_fma(sim, wxy, im);
-        }
-    }
-    const double n2d = (double)n2;
-    const double f = h1 * h1 * h1 / (n2d * n2d * n2d) * phi_inv[k];
-    out[k] = make_double2(re * f, im * f);
+    m %= n;
+    return m < 0 ? m + n : m;
 }
 
-// Morton key (10 bits per axis) of each node's cell of 2 grid points at the
-// grid scale n2 h1 / (2 pi), with its index, for the sort behind k_interp's
-// node order.
-__device__ __forceinline__ unsigned morton_spread10(unsigned v)
-{
-    v &= 1023u;
-    v = (v | (v << 16)) & 0x030000FFu;
-    v = (v | (v << 8)) & 0x0300F00Fu;
-    v = (v | (v << 4)) & 0x030C30C3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
-}
-
-__global__ __launch_bounds__(256) void k_node_keys(const double *__restrict__ dirs, const double *__restrict__ radii,
-                                                   int n_rad, int64_t N, double scale, int n2,
-                                                   unsigned *__restrict__ keys, int *__restrict__ idx)
+// tile key of every target's stencil origin, with its index
+__global__ __launch_bounds__(256) void k_target_tiles(const double *__restrict__ dirs, const double *__restrict__ radii,
+                                                      int n_rad, int64_t N, double scale, int w, int H, int TS,
+                                                      int nt1, int *__restrict__ keys, int *__restrict__ idx)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
     const int64_t d = k / n_rad;
     const double r = radii[k - d * n_rad];
-    unsigned key = 0;
+    int key = 0;
     for (int a = 0; a < 3; ++a) {
-        const double u = r * dirs[3 * d + a] * scale + 0.5 * n2;
-        const int c = (int)floor(u) >> 1;
-        key |= morton_spread10((unsigned)(c < 0 ? 0 : (c > 1023 ? 1023 : c))) << a;
+        const double u = r * dirs[3 * d + a] * scale;
+        const int lo = (int)ceil(u - 0.5 * w);
+        int c = (lo + H) / TS;
+        c = c < 0 ? 0 : (c >= nt1 ? nt1 - 1 : c);
+        key = key * nt1 + c;
     }
     keys[k] = key;
     idx[k] = (int)k;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine, int n2, const double *__restrict__ dirs,
+                                                const double *__restrict__ radii, int n_rad, double h1, double beta,
+                                                const double *__restrict__ phi_inv, const int *__restrict__ order,
+                                                const int4 *__restrict__ items, int H, int nt1,
+                                                double2 *__restrict__ out)
+{
+    constexpr int TS = interp_tile<W>(), B = TS + W - 1;
+    __shared__ double2 box[B * B * B];
+    const int4 it = items[blockIdx.x];   // (tile, first target, end, 0) in the sorted order
+    const int tile = it.x;
+    const int o[3] = {(tile / (nt1 * nt1)) * TS - H, ((tile / nt1) % nt1) * TS - H, (tile % nt1) * TS - H};
+    for (int e = threadIdx.x; e < B * B * B; e += blockDim.x) {
+        const int bz = e % B, by = (e / B) % B, bx = e / (B * B);
+        box[e] = fine[((int64_t)wrap_index(o[0] + bx, n2) * n2 + wrap_index(o[1] + by, n2)) * n2 +
+                      wrap_index(o[2] + bz, n2)];
+    }
+    __syncthreads();
+    const double half_w = 0.5 * W;
+    const double iw = 1.0 / half_w;
+    const double scale = (double)n2 * h1 / (2.0 * kPi);
+    const double n2d = (double)n2;
+    const double fscale = h1 * h1 * h1 / (n2d * n2d * n2d);
+    for (int t = it.y + (int)threadIdx.x; t < it.z; t += blockDim.x) {
+        const int k = order[t];
+        const int d = k / n_rad;
+        const double r = radii[k - d * n_rad];
+        double wt[3][W];
+        int b[3];
+        for (int a = 0; a < 3; ++a) {
+            const double u = r * dirs[3 * d + a] * scale;
+            const int lo = (int)ceil(u - half_w);
+            // in [0, TS) by the tile choice (|u| <= n2 / (2 sigma)); the clamp
+            // only keeps every LDS read inside the box
+            const int bb = lo - o[a];
+            b[a] = bb < 0 ? 0 : (bb > TS - 1 ? TS - 1 : bb);
+#pragma unroll
+            for (int i = 0; i < W; ++i) wt[a][i] = es_eval(((double)(lo + i) - u) * iw, beta);
+        }
+        double re = 0.0, im = 0.0;
+        for (int i = 0; i < W; ++i) {
+            for (int j = 0; j < W; ++j) {
+                const double wxy = wt[0][i] * wt[1][j];
+                const double2 *row = box + ((b[0] + i) * B + (b[1] + j)) * B + b[2];
+                double sre = 0.0, sim = 0.0;
+#pragma unroll
+                for (int l = 0; l < W; ++l) {
+                    const double2 v = row[l];
+                    sre = __builtin_fma(v.x, wt[2][l], sre);
+                    sim = __builtin_fma(v.y, wt[2][l], sim);
+                }
+                re = __builtin_fma(sre, wxy, re);
+                im = __builtin_fma(sim, wxy, im);
+            }
+        }
+        const double f = fscale * phi_inv[k];
+        out[k] = make_double2(re * f, im * f);
+    }
 }
 
 // 1 / Phi^(xi_k) per node, Phi^(xi) = prod_a (w h1 / 2) 2 sum_q wpsi_q
@@ -768,67 +773,99 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     }
     const double *dirs = sp ? rule->d_dirs.as<const double>() : rule->d_nodes.as<const double>();
     const int n_rad = sp ? (int)rule->n_rad : 1;
+    // interpolation tiles: TS^3 stencil origins per tile, nt1 tiles per axis
+    // over the shifted origins lo + H in [0, n2 + w + 2)
+    const int TS = std::max(18 - w, 2);
+    const int H = n2 / 2 + w;
+    const int nt1 = (n2 + 2 * w + TS) / TS;
+    if ((int64_t)nt1 * nt1 * nt1 > INT32_MAX || N > INT32_MAX) {
+        set_error("NUFFT: too many nodes or interpolation tiles");
+        return HSD_EINVAL;
+    }
     const double *phi_inv = nullptr;
     const int *order = nullptr;
+    const int4 *items = nullptr;
+    int nitems = 0;
     {
         hsd_rule *rm = const_cast<hsd_rule *>(rule);
         std::lock_guard<std::mutex> lk(rm->mu);
         for (const auto &e : rm->nufft_deconv)
-            if (e->w == w && e->beta == beta && e->h1 == h1) {
+            if (e->w == w && e->beta == beta && e->h1 == h1 && e->n2 == n2) {
                 phi_inv = e->inv.as<const double>();
                 order = e->order.as<const int>();
+                items = e->items.as<const int4>();
+                nitems = e->nitems;
             }
-        if (!phi_inv) {
-            if (N > INT32_MAX) {
-                set_error("NUFFT: too many nodes");
-                return HSD_EINVAL;
-            }
+        if (!phi_inv && N > 0) {
             std::unique_ptr<hsd_rule::NufftDeconv> e(new hsd_rule::NufftDeconv());
             e->w = w;
             e->beta = beta;
             e->h1 = h1;
+            e->n2 = n2;
             const dim3 ng((unsigned)((N + 255) / 256)), nb(256);
             if ((stt = e->inv.alloc(ctx, (size_t)N * sizeof(double))) != HSD_OK) return stt;
             hipLaunchKernelGGL(k_phi_inv, ng, nb, 0, st, dirs, rule->d_radii.as<const double>(), n_rad, N, h1, w,
                                sc.ftq.as<const double2>(), (int)ftq.size(), e->inv.as<double>());
             HSD_HIP_TRY(hipGetLastError());
-            // node order for the interpolation: Morton order of the cells at
-            // this call's grid scale (any order is correct; later calls with
-            // another fine-grid size reuse it)
+            // targets grouped by interpolation tile (stable sort: ascending
+            // node index within a tile), then cut into work items
             DevBuf keys, keys2, idx, tmp;
-            if ((stt = keys.alloc(ctx, (size_t)N * sizeof(unsigned))) != HSD_OK) return stt;
-            if ((stt = keys2.alloc(ctx, (size_t)N * sizeof(unsigned))) != HSD_OK) return stt;
+            if ((stt = keys.alloc(ctx, (size_t)N * sizeof(int))) != HSD_OK) return stt;
+            if ((stt = keys2.alloc(ctx, (size_t)N * sizeof(int))) != HSD_OK) return stt;
             if ((stt = idx.alloc(ctx, (size_t)N * sizeof(int))) != HSD_OK) return stt;
             if ((stt = e->order.alloc(ctx, (size_t)N * sizeof(int))) != HSD_OK) return stt;
-            hipLaunchKernelGGL(k_node_keys, ng, nb, 0, st, dirs, rule->d_radii.as<const double>(), n_rad, N,
-                               (double)n2 * h1 / (2.0 * kPi), n2, keys.as<unsigned>(), idx.as<int>());
+            hipLaunchKernelGGL(k_target_tiles, ng, nb, 0, st, dirs, rule->d_radii.as<const double>(), n_rad, N,
+                               (double)n2 * h1 / (2.0 * kPi), w, H, TS, nt1, keys.as<int>(), idx.as<int>());
             HSD_HIP_TRY(hipGetLastError());
+            int key_bits = 1;
+            while (((int64_t)1 << key_bits) < (int64_t)nt1 * nt1 * nt1) ++key_bits;
             size_t tmp_bytes = 0;
-            HSD_HIP_TRY(rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys.as<unsigned>(), keys2.as<unsigned>(),
-                                                  idx.as<int>(), e->order.as<int>(), (unsigned int)N, 0, 30, st));
+            HSD_HIP_TRY(rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys.as<int>(), keys2.as<int>(), idx.as<int>(),
+                                                  e->order.as<int>(), (unsigned int)N, 0, key_bits, st));
             if ((stt = tmp.alloc(ctx, std::max<size_t>(tmp_bytes, 8))) != HSD_OK) return stt;
-            HSD_HIP_TRY(rocprim::radix_sort_pairs(tmp.ptr, tmp_bytes, keys.as<unsigned>(), keys2.as<unsigned>(),
-                                                  idx.as<int>(), e->order.as<int>(), (unsigned int)N, 0, 30, st));
+            HSD_HIP_TRY(rocprim::radix_sort_pairs(tmp.ptr, tmp_bytes, keys.as<int>(), keys2.as<int>(), idx.as<int>(),
+                                                  e->order.as<int>(), (unsigned int)N, 0, key_bits, st));
+            std::vector<int> sk((size_t)N);
+            HSD_HIP_TRY(hipMemcpyAsync(sk.data(), keys2.ptr, (size_t)N * sizeof(int), hipMemcpyDeviceToHost, st));
+            HSD_HIP_TRY(hipStreamSynchronize(st));
+            constexpr int kItemTargets = 1024;   // targets per interpolation work item (at most)
+            std::vector<int4> it;
+            for (int64_t a = 0; a < N;) {
+                int64_t b = a + 1;
+                while (b < N && sk[(size_t)b] == sk[(size_t)a]) ++b;
+                for (int64_t c = a; c < b; c += kItemTargets)
+                    it.push_back(make_int4(sk[(size_t)a], (int)c, (int)std::min<int64_t>(b, c + kItemTargets), 0));
+                a = b;
+            }
+            e->nitems = (int)it.size();
+            if ((stt = e->items.alloc(ctx, std::max<size_t>(it.size(), 1) * sizeof(int4))) != HSD_OK) return stt;
+            if (!it.empty())
+                HSD_HIP_TRY(hipMemcpyAsync(e->items.ptr, it.data(), it.size() * sizeof(int4), hipMemcpyHostToDevice, st));
             // complete before other streams (serving slots) may read them and
             // before the temporaries are freed
             HSD_HIP_TRY(hipStreamSynchronize(st));
             phi_inv = e->inv.as<const double>();
             order = e->order.as<const int>();
+            items = e->items.as<const int4>();
+            nitems = e->nitems;
             rm->nufft_deconv.push_back(std::move(e));
         }
     }
-    const dim3 ig((unsigned)((N + 255) / 256)), ib(256);
-    const double2 *fg = sc.fine.as<const double2>();
-    const double *rr = rule->d_radii.as<const double>();
-    switch (w) {
-#define HSD_INTERP_W(WW)                                                                                        \
-    case WW: hipLaunchKernelGGL(k_interp<WW>, ig, ib, 0, st, fg, n2, dirs, rr, n_rad, N, h1, beta, phi_inv, order, out); \
+    if (nitems > 0) {
+        const dim3 ig((unsigned)nitems), ib(256);
+        const double2 *fg = sc.fine.as<const double2>();
+        const double *rr = rule->d_radii.as<const double>();
+        switch (w) {
+#define HSD_INTERP_W(WW)                                                                                     \
+    case WW: hipLaunchKernelGGL(k_interp<WW>, ig, ib, 0, st, fg, n2, dirs, rr, n_rad, h1, beta, phi_inv, order, \
+                                items, H, nt1, out);                                                       \
         break;
-        HSD_INTERP_W(2) HSD_INTERP_W(3) HSD_INTERP_W(4) HSD_INTERP_W(5) HSD_INTERP_W(6) HSD_INTERP_W(7)
-        HSD_INTERP_W(8) HSD_INTERP_W(9) HSD_INTERP_W(10) HSD_INTERP_W(11) HSD_INTERP_W(12) HSD_INTERP_W(13)
-        HSD_INTERP_W(14) HSD_INTERP_W(15) HSD_INTERP_W(16)
+            HSD_INTERP_W(2) HSD_INTERP_W(3) HSD_INTERP_W(4) HSD_INTERP_W(5) HSD_INTERP_W(6) HSD_INTERP_W(7)
+            HSD_INTERP_W(8) HSD_INTERP_W(9) HSD_INTERP_W(10) HSD_INTERP_W(11) HSD_INTERP_W(12) HSD_INTERP_W(13)
+            HSD_INTERP_W(14) HSD_INTERP_W(15) HSD_INTERP_W(16)
 #undef HSD_INTERP_W
-    default: set_error("NUFFT width %d unsupported", w); return HSD_EINVAL;
+        default: set_error("NUFFT width %d unsupported", w); return HSD_EINVAL;
+        }
     }
     HSD_HIP_TRY(hipGetLastError());
     if (pairs) *pairs = (double)np;
