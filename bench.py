@@ -43,12 +43,12 @@ WORKLOADS = {
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (256 CU x 2.4 GHz x 128 FLOP/clk)
 
-# HBM bytes per launch of k_direct_wave<2,FP64> measured with rocprofv3 for the
+# HBM bytes per launch of k_direct_wave<2> (FP64) measured with rocprofv3 for the
 # current kernel revision: FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the factors
 # read off a 1 GiB device copy in the same runs
 # (profiles/k_direct_wave_fp64_level7_large_rule.md).  Re-measure after any
 # change to the kernel; other workloads were not measured.
-MEASURED_TRAFFIC = {"level7-large-rule": (3246006.1875 * 2.0 + 131072.0) * 1024.0}
+MEASURED_TRAFFIC = {"level7-large-rule": (3246995.5625 * 2.0 + 131072.0) * 1024.0}
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (256 CU x 2.4 GHz x 256 FLOP/clk)
 
 
@@ -164,7 +164,7 @@ def main():
                        "traffic": MEASURED_TRAFFIC.get(args.workload),
                        "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, "
                                        "scaled by a plain copy's counters",
-                       "kernel": "k_direct_wave<FP64>", "kernel_ms": kern_ms,
+                       "kernel": "k_direct_wave (FP64)", "kernel_ms": kern_ms,
                        "flops_per_pair": flop_pair}
     if not args.no_mixed:
         mixed = hsd.Params(s=1.0, form="mixed")
@@ -179,7 +179,7 @@ def main():
                         "speedup_vs_fp64": wall64 / wallm, "kernel_ms": kern_m,
                         "roofline": {"bound": "alu", "achieved": ach_m, "peak": FP32_PEAK_TFLOPS,
                                      "unit": "TFLOP/s", "frac": ach_m / FP32_PEAK_TFLOPS,
-                                     "kernel": "k_direct_wave<MIXED>",
+                                     "kernel": "k_direct_wave_mixed",
                                      "note": "FP32 peak; the kernel's FP64 phase reduction and "
                                              "FP64 accumulation run at the FP64 rate"}}
     if not args.no_nufft:
