@@ -136,6 +136,29 @@ def test_nufft_off_centre_mesh(hsd_ctx, orc, kind):
     rule.close()
 
 
+def test_nufft_rule_shared_by_meshes_of_different_extent(hsd_ctx, orc):
+    """One ball rule used in turn by meshes of radius 1 and 2.5: their fine
+    grids differ in size, so the rule's cached interpolation grouping (by
+    kernel and grid size) must not be reused across them.  Each transform
+    against the oracle's direct point sum, twice in alternation."""
+    rule = hsd.Rule.spherical_product(hsd_ctx, **SPEC)
+    nodes = orc.spherical_product_rule(**SPEC).nodes
+    v, f = icosphere(2)
+    meshes = [(v, f), (v * 2.5, f)]
+    refs = []
+    for vv, ff in meshes:
+        pts, c = orc.point_cloud(vv, ff, "gl8x8")
+        refs.append((orc.point_sum(pts, c, nodes), np.sum(np.abs(c))))
+    p = hsd.Params(method="nufft3", tri_rule="gl8x8", nufft_tol=1e-9)
+    for _ in range(2):
+        for (vv, ff), (ref, norm) in zip(meshes, refs):
+            mesh = hsd.Mesh(hsd_ctx, vv, ff)
+            got = hsd.transform_rule(hsd_ctx, mesh, rule, p)
+            assert np.max(np.abs(got - ref)) <= 1e-9 * norm
+            mesh.close()
+    rule.close()
+
+
 def test_nufft_distance_model_error_and_determinism(hsd_ctx, orc):
     """d^2 from the NUFFT path vs (i) the same d^2 from the direct point sum
     (NUFFT error, pinned) and (ii) the exact-triangle d^2 (the point-rule
