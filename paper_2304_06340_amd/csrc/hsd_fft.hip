@@ -23,7 +23,7 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b)
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-constexpr int kFftMaxElems = 4096;   // complex values per block tile (64 KB of LDS)
+constexpr int kFftMaxElems = 4374;   // complex values per block tile (68 KB of LDS: two blocks per CU)
 
 // One Stockham stage of radix R on Bt lines of length n in LDS: every
 // thread first gathers (and twiddles) the inputs of all its butterflies into
