@@ -58,6 +58,13 @@ constexpr double kLog2E = 1.4426950408889634;     // RN(1 / ln 2)
 constexpr double kLn2Hi = 0.6931471805599453;     // RN(ln 2)
 constexpr double kLn2Lo = 2.3190468138462996e-17; // RN(ln 2 - kLn2Hi)
 
+// 1/k!, k = 0..11, in constant memory: read with scalar loads, so that the
+// Horner steps take them from scalar registers instead of rebuilding 64-bit
+// literals in vector registers on every evaluation.
+__constant__ double kExpTaylor[12] = {inv_factorial(0), inv_factorial(1), inv_factorial(2),  inv_factorial(3),
+                                      inv_factorial(4), inv_factorial(5), inv_factorial(6),  inv_factorial(7),
+                                      inv_factorial(8), inv_factorial(9), inv_factorial(10), inv_factorial(11)};
+
 HSD_HD double es_eval(double z, double beta)
 {
     const double a = __builtin_fma(-z, z, 1.0);
@@ -73,9 +80,9 @@ HSD_HD double es_eval(double z, double beta)
     const double n = __builtin_rint(x * kLog2E);
     double r = __builtin_fma(-n, kLn2Hi, x);
     r = __builtin_fma(-n, kLn2Lo, r);
-    double pe = inv_factorial(11);
+    double pe = kExpTaylor[11];
 #pragma unroll
-    for (int k = 10; k >= 0; --k) pe = __builtin_fma(pe, r, inv_factorial(k));
+    for (int k = 10; k >= 0; --k) pe = __builtin_fma(pe, r, kExpTaylor[k]);
     const double v = ldexp(pe, (int)n);
     return a > 0.0 ? v : 0.0;
 #else
