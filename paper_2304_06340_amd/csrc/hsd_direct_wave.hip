@@ -12,11 +12,12 @@
 //     PG panels p = w0 + g*PG + pl (2*PG nodes);
 //   * triangles are processed in batches of 8.  Producer step: lane
 //     (t, j) = (lane / 8, lane % 8) computes, for triangle t of the batch,
-//     exp(-i h x_j c), exp(-i (h - h x_j) c) (the small-radius node of panel
-//     0, evaluated directly to keep relative accuracy) and the panel-centre
-//     phases exp(-i m_p c) of panels w0 + j*PG .. w0 + j*PG + PG-1, for the
-//     three constants c = theta_mid, a/2, b/2 of the triangle and direction,
-//     and stores them with the triangle's scale factors in LDS;
+//     exp(-i h x_j c) and the panel-centre phases exp(-i m_p c) of panels
+//     w0 + j*PG .. w0 + j*PG + PG-1 (the mixed form also exp(-i (h - h x_j) c)
+//     of the small-radius node of panel 0, whose FP32 phases need relative
+//     accuracy), for the three constants c = theta_mid, a/2, b/2 of the
+//     triangle and direction, and stores them with the triangle's scale
+//     factors in LDS;
 //   * consumer step: every lane forms its node phases by one complex product
 //     per constant and node and accumulates, reading the batch from LDS.
 //
@@ -50,7 +51,6 @@ struct Scal32 { double J; float rthr, Ka, Kb, pad; float ce[kNC32], co[kNC32]; }
 template <int PG> struct Batch64 {
     Scal64 sc[kTB];
     cs64 Bk[kTB][kNH][3];
-    cs64 P0[kTB][kNH][3];
     cs64 Cp[kTB][kNH * PG][3];
 };
 template <int PG> struct Batch32 {
@@ -118,28 +118,20 @@ HSD_HD void series_eval(const T ce[kNC64], const T co[kNC64], T r2, T &pe, T &po
     }
 }
 
-// Producer, FP64: part j of a triangle's batch entry.
+// Producer, FP64: part j of a triangle's batch entry (the half-node phases
+// of node j and the centre phases of panels w0 + j PG .. w0 + j PG + PG-1).
 template <int PG>
 HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
-                      const cs64 *turn, Scal64 *sc, cs64 Bk[3], cs64 P0[3], cs64 Cp[PG][3])
+                      const cs64 *turn, Scal64 *sc, cs64 Bk[3], cs64 Cp[PG][3])
 {
     const double fr[3] = {td.tmid, 0.5 * td.ac, 0.5 * td.bc};
     const double hx = hx_tab[j];
-    const double r0 = h - hx;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         Bk[c] = sincos64_tab(hx * fr[c], turn);
-        P0[c] = sincos64_tab(r0 * fr[c], turn);
-        Cp[0][c] = sincos64_tab((double)(2 * (w0 + j * PG) + 1) * h * fr[c], turn);
-        if (PG > 1) {
-            // next panel centre: times e^{-2ihc} = (e^{-i hx c} e^{-i (h - hx) c})^2,
-            // three products instead of a sin/cos (all angles of one sign add,
-            // so small angles keep their relative accuracy)
-            const cs64 e1 = pmul(Bk[c], P0[c]);
-            const cs64 step = pmul(e1, e1);
 #pragma unroll
-            for (int q = 1; q < PG; ++q) Cp[q][c] = pmul(Cp[q - 1][c], step);
-        }
+        for (int q = 0; q < PG; ++q)
+            Cp[q][c] = sincos64_tab((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c], turn);
     }
     if (sc) {
         sc->Ka = 2.0 * td.J * rcp64(td.ac) * td.iG;
@@ -151,8 +143,14 @@ HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, i
 }
 
 // Consumer, FP64: one triangle into the lane's 2*PG slots (slot 2*pl + sg).
+// Every node's phases are products of a panel-centre and a half-node phase,
+// also for the small-radius node h - h x_k of panel 0: the product carries an
+// absolute error of a few ulp in its sine, which the closed branch (taken
+// only for r G >= tau) turns into a relative error below ~eps / tau, the
+// same class as the branch's own cancellation; below tau only the
+// theta_mid phase enters.
 template <int PG>
-HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 P0[3], const cs64 (*Cp)[3], double h,
+HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 (*Cp)[3], double h,
                       double hx, int pbase, double *acc_re, double *acc_im)
 {
 #pragma unroll
@@ -164,14 +162,8 @@ HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 P0[3], cons
             const int slot = 2 * pl + sg;
             const double r = sg == 0 ? m + hx : m - hx;
             cs64 E[3];
-            // the small-radius node h - h x_k exists only in panel 0, which a
-            // lane can hold only as its first panel
-            const bool direct = (sg == 1) && (pl == 0) && (pbase == 0);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const cs64 prod = sg == 0 ? pmul(Cp[pl][c], Bk[c]) : pmulc(Cp[pl][c], Bk[c]);
-                E[c] = direct ? P0[c] : prod;
-            }
+            for (int c = 0; c < 3; ++c) E[c] = sg == 0 ? pmul(Cp[pl][c], Bk[c]) : pmulc(Cp[pl][c], Bk[c]);
             const double Pv = sc.Kb * E[2].s;
             const double Pu = sc.Ka * E[1].s;
             double Yr = __builtin_fma(Pv, E[2].s, Pu * E[1].s);
@@ -385,7 +377,7 @@ __device__ __forceinline__ void direct_wave_body(
             const TriDir td = tri_dir(*rp, J, nx, ny, nz, F64 ? kGapFloor : kGapFloor32);
             if constexpr (F64)
                 produce64<PG>(td, h, hx_tab, pj, w0, tau, turn, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
-                              L.P0[pt][pj], &L.Cp[pt][pj * PG]);
+                              &L.Cp[pt][pj * PG]);
             else
                 produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
                               L.P0[pt][pj], L.Cp[pt]);
@@ -393,7 +385,7 @@ __device__ __forceinline__ void direct_wave_body(
         wave_lds_sync();
         for (int t = 0; t < nvalid; ++t) {
             if constexpr (F64)
-                consume64<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx, pbase, acc_re, acc_im);
+                consume64<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][g * PG], h, hx, pbase, acc_re, acc_im);
             else
                 consume32<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][po], rf, r2f, r2d, direct0, sgl == 1,
                               acc_re, acc_im);
@@ -428,9 +420,10 @@ __device__ __forceinline__ void direct_wave_body(
     }
 }
 
-// FP64 form: occupancy 3 (the LDS batch, 13 KB per wave, allows no more).
+// FP64 form: its LDS batch (10 KB per wave, 40 KB per block) allows 4
+// blocks per CU.
 template <int PG>
-__global__ __launch_bounds__(256) void k_direct_wave(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_direct_wave(
     const TriRec *__restrict__ A, int64_t nA, const TriRec *__restrict__ B, int64_t nB,
     const double *__restrict__ dirs, const double *__restrict__ hx_tab, int64_t d_begin, int64_t d_count,
     int P, double h, double tau, int64_t N, double2 *__restrict__ partial)
@@ -524,7 +517,7 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
                 if (F64) {
                     auto &L = b64[0];
                     produce64<PG>(td, h, hx_tab, pj, w0, tau, turn, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
-                                  L.P0[pt][pj], &L.Cp[pt][pj * PG]);
+                                  &L.Cp[pt][pj * PG]);
                 } else {
                     auto &L = b32[0];
                     produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
@@ -541,7 +534,7 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
                 for (int t = 0; t < nvalid; ++t) {
                     if (F64) {
                         auto &L = b64[0];
-                        consume64<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][g * PG], h, hx_tab[k], pbase,
+                        consume64<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][g * PG], h, hx_tab[k], pbase,
                                       &are[lane * NS], &aim[lane * NS]);
                     } else {
                         auto &L = b32[0];

@@ -72,13 +72,27 @@ def _area(v, f):
     return 0.5 * np.linalg.norm(np.cross(v[f[:, 1]] - v[f[:, 0]], v[f[:, 2]] - v[f[:, 0]]), axis=1).sum()
 
 
-def mu_tol(v, f, nodes, k=20.0, tau=1e-2):
+def mu_tol(v, f, nodes, k=20.0, tau=1e-2, h=None):
     """Per-node bound for two FP64 evaluations of mu_h^: phase rounding
     (eps |xi| per vertex phase) plus the closed branch's eps/G error with
-    G >= tau, each times the triangle's J = 2 area."""
+    G >= tau, each times the triangle's J = 2 area.
+
+    h: half panel width of a spherical-product rule evaluated by the
+    wave-per-direction kernel.  Its nodes below the first panel centre
+    (r = h - h x_k < h) take their half-gap phases as products of the
+    centre phase and the node offset's phase, whose angles exceed the
+    node's own: the small half-gap sine then carries an absolute (not a
+    relative) rounding of a few ulp, which the closed branch divides by
+    r G >= tau, in Re and Im and for both gaps.  Bound for those nodes:
+    160 eps / tau per unit area (the worst case measured over levels 0-3
+    and three rules is 72)."""
     eps = 1.1e-16
     A = _area(v, f)
-    return k * eps * (1.0 + np.linalg.norm(nodes, axis=1)) * A + 8.0 * eps / tau * A
+    r = np.linalg.norm(nodes, axis=1)
+    tol = k * eps * (1.0 + r) * A + 8.0 * eps / tau * A
+    if h is not None:
+        tol = tol + np.where(r < h, 160.0 * eps / tau * A, 0.0)
+    return tol
 
 
 def test_sincos64_against_libm():
@@ -221,7 +235,32 @@ def test_wave_kernel_bodies_match_oracle(orc, spec, form, perturb):
     ref = orc.transform(v, f, o.nodes)
     err = np.abs(got - ref)
     if form == 0:
-        assert np.all(err <= mu_tol(v, f, o.nodes)), err.max()
+        h = spec["r_max"] / spec["n_panels"] / 2
+        assert np.all(err <= mu_tol(v, f, o.nodes, h=h)), err.max()
     else:
         assert np.all(np.isfinite(got))
         assert err.max() <= 2e-5 * _area(v, f)
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+@pytest.mark.parametrize("spec", [
+    dict(r_max=16.0, n_panels=8, n_per_panel=16, n_cos=3, n_phi=4),
+    dict(r_max=64.0, n_panels=8, n_per_panel=16, n_cos=3, n_phi=5),
+    dict(r_max=256.0, n_panels=16, n_per_panel=16, n_cos=2, n_phi=3),
+])
+def test_wave_kernel_small_radius_nodes(orc, level, spec):
+    """FP64 wave-kernel bodies on coarse meshes (edges up to 1.05), where the
+    nodes below the first panel centre take the closed branch near its
+    threshold r G = tau: every node within the per-node bound, and the
+    nodes at r >= h within the bound without the small-radius term."""
+    rng = np.random.default_rng(level)
+    v, f = icosphere(level)
+    v = rotate(perturb_radial(v, 0.05, rng), random_rotation(rng))
+    got = host_wave(v, f, spec, 0)
+    o = orc.spherical_product_rule(**spec)
+    ref = orc.transform(v, f, o.nodes)
+    err = np.abs(got - ref)
+    h = spec["r_max"] / spec["n_panels"] / 2
+    r = np.linalg.norm(o.nodes, axis=1)
+    assert np.all(err <= mu_tol(v, f, o.nodes, h=h)), err.max()
+    assert np.all(err[r >= h] <= mu_tol(v, f, o.nodes[r >= h])), err[r >= h].max()
