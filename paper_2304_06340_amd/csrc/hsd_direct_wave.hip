@@ -12,10 +12,9 @@
 //     PG panels p = w0 + g*PG + pl (2*PG nodes);
 //   * triangles are processed in batches of 8.  Producer step: lane
 //     (t, j) = (lane / 8, lane % 8) computes, for triangle t of the batch,
-//     exp(-i h x_j c) and the panel-centre phases exp(-i m_p c) of panels
-//     w0 + j*PG .. w0 + j*PG + PG-1 (the mixed form also exp(-i (h - h x_j) c)
-//     of the small-radius node of panel 0, whose FP32 phases need relative
-//     accuracy), for the three constants c = theta_mid, a/2, b/2 of the
+//     exp(-i h x_j c) and the panel-centre phases exp(-i m_p c) of its PG
+//     panels (panels w0 + j*PG + q in the FP64 form, w0 + j + 8 q in the
+//     mixed form), for the three constants c = theta_mid, a/2, b/2 of the
 //     triangle and direction, and stores them with the triangle's scale
 //     factors in LDS;
 //   * consumer step: every lane forms its node phases by one complex product
@@ -56,7 +55,6 @@ template <int PG> struct Batch64 {
 template <int PG> struct Batch32 {
     Scal32 sc[kTB];
     cs32 Bk[kTB][kNH][3];
-    cs32 P0[kTB][kNH][3];
     cs32 Cp[kTB][kNH * PG][3];
 };
 
@@ -186,18 +184,13 @@ HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 (*Cp)[3], d
 // panels j + kNH q.
 template <int PG>
 HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
-                      Scal32 *sc, cs32 Bk[3], cs32 P0[3], cs32 (*Cp)[3])
+                      Scal32 *sc, cs32 Bk[3], cs32 (*Cp)[3])
 {
     const double fr[3] = {td.tmid, 0.5 * td.ac, 0.5 * td.bc};
     const double hx = hx_tab[j];
-    const double r0 = h - hx;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         Bk[c] = sincos32_acc(hx * fr[c]);
-        // small-radius node of panel 0: its half-gap phases directly (they
-        // need relative accuracy); its theta_mid phase is formed by the
-        // consumer's product like every other node's
-        if (c > 0) P0[c] = sincos32_acc(r0 * fr[c]);
 #pragma unroll
         for (int q = 0; q < PG; ++q)
             Cp[j + kNH * q][c] = sincos32_acc((double)(2 * (w0 + j + kNH * q) + 1) * h * fr[c]);
@@ -230,9 +223,15 @@ HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, i
 // quarter of the wave's radial range, so that the series threshold r G = tau
 // splits one slot per triangle and the others take one branch only.  The
 // half-gap phases are formed only where some lane takes the closed branch.
+//
+// All node phases are products of a panel-centre and a node-offset phase,
+// also for the small-radius nodes h - h x_k of panel 0, whose small half-gap
+// sines then carry an absolute FP32 rounding: the closed branch (r G >= 0.75
+// in this form) enlarges it by at most 1 / (r G), the size of the rounding
+// every other node's closed branch carries.
 template <int PG>
-HSD_HD void consume32(const Scal32 &scr, const cs32 Bk[3], const cs32 P0[3], const cs32 (*Cp)[3],
-                      const float *rf, const float *r2f, const double *r2d, bool direct0,
+HSD_HD void consume32(const Scal32 &scr, const cs32 Bk[3], const cs32 (*Cp)[3],
+                      const float *rf, const float *r2f, const double *r2d,
                       bool conj, double *acc_re, double *acc_im)
 {
     constexpr int NS = 2 * PG;
@@ -242,9 +241,8 @@ HSD_HD void consume32(const Scal32 &scr, const cs32 Bk[3], const cs32 P0[3], con
     for (int c = 0; c < 3; ++c) B[c] = cs32{Bk[c].c, conj ? -Bk[c].s : Bk[c].s};
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
-        const bool direct = q == 0 && direct0;   // the node h - h x_k of panel 0
         const cs32 E0 = pmul(Cp[4 * q][0], B[0]);
-        float Yr, Xr, half;
+        float tre, tim;
         double scale;
         if (rf[q] < sc.rthr) {
             // Re of the series minus its constant 1/2; the 1/2 term is added
@@ -258,26 +256,23 @@ HSD_HD void consume32(const Scal32 &scr, const cs32 Bk[3], const cs32 P0[3], con
             for (int m = kNC32 - 2; m >= 1; --m) pe = __builtin_fmaf(pe, r2, sc.ce[m]);
 #pragma unroll
             for (int m = kNC32 - 2; m >= 0; --m) po = __builtin_fmaf(po, r2, sc.co[m]);
-            Yr = pe * r2;
-            Xr = rf[q] * po;
-            half = 0.5f;
+            const float Yr = pe * r2;
+            const float Xr = rf[q] * po;
+            tre = __builtin_fmaf(0.5f, E0.c, __builtin_fmaf(E0.c, Yr, E0.s * Xr));
+            tim = __builtin_fmaf(-0.5f, E0.s, __builtin_fmaf(E0.c, Xr, -E0.s * Yr));
             scale = r2d[q] * sc.J;
         } else {
             cs32 E[3];
 #pragma unroll
-            for (int c = 1; c < 3; ++c) {
-                const cs32 prod = pmul(Cp[4 * q][c], B[c]);
-                E[c] = direct ? P0[c] : prod;
-            }
+            for (int c = 1; c < 3; ++c) E[c] = pmul(Cp[4 * q][c], B[c]);
             const float Pv = sc.Kb * E[2].s;
             const float Pu = sc.Ka * E[1].s;
-            Yr = __builtin_fmaf(Pv, E[2].s, Pu * E[1].s);
-            Xr = __builtin_fmaf(Pv, E[2].c, -Pu * E[1].c);
-            half = 0.0f;
+            const float Yr = __builtin_fmaf(Pv, E[2].s, Pu * E[1].s);
+            const float Xr = __builtin_fmaf(Pv, E[2].c, -Pu * E[1].c);
+            tre = __builtin_fmaf(E0.c, Yr, E0.s * Xr);
+            tim = __builtin_fmaf(E0.c, Xr, -E0.s * Yr);
             scale = sc.J;
         }
-        const float tre = __builtin_fmaf(half, E0.c, __builtin_fmaf(E0.c, Yr, E0.s * Xr));
-        const float tim = __builtin_fmaf(-half, E0.s, __builtin_fmaf(E0.c, Xr, -E0.s * Yr));
         acc_re[q] = __builtin_fma(scale, (double)tre, acc_re[q]);
         acc_im[q] = __builtin_fma(scale, (double)tim, acc_im[q]);
     }
@@ -354,7 +349,6 @@ __device__ __forceinline__ void direct_wave_body(
     double r2d[F64 ? 1 : NS];
     float rf[F64 ? 1 : NS], r2f[F64 ? 1 : NS];
     if constexpr (!F64) mixed_lane_radii<PG>(w0, po, sgl, h, hx, rf, r2f, r2d);
-    const bool direct0 = w0 == 0 && po == 0 && sgl == 1;
     auto &L = lds[w];
 
     const int64_t ntot = nA + nB;
@@ -380,15 +374,14 @@ __device__ __forceinline__ void direct_wave_body(
                               &L.Cp[pt][pj * PG]);
             else
                 produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
-                              L.P0[pt][pj], L.Cp[pt]);
+                              L.Cp[pt]);
         }
         wave_lds_sync();
         for (int t = 0; t < nvalid; ++t) {
             if constexpr (F64)
                 consume64<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][g * PG], h, hx, pbase, acc_re, acc_im);
             else
-                consume32<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][po], rf, r2f, r2d, direct0, sgl == 1,
-                              acc_re, acc_im);
+                consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1, acc_re, acc_im);
         }
         wave_lds_sync();
         if (++nb == kTileBatches) {
@@ -521,7 +514,7 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
                 } else {
                     auto &L = b32[0];
                     produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
-                                  L.P0[pt][pj], L.Cp[pt]);
+                                  L.Cp[pt]);
                 }
             }
             for (int lane = 0; lane < 64; ++lane) {
@@ -538,8 +531,8 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
                                       &are[lane * NS], &aim[lane * NS]);
                     } else {
                         auto &L = b32[0];
-                        consume32<PG>(L.sc[t], L.Bk[t][k], L.P0[t][k], &L.Cp[t][po], rf, r2f, r2d,
-                                      w0 == 0 && po == 0 && sgl == 1, sgl == 1, &are[lane * NS], &aim[lane * NS]);
+                        consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1,
+                                      &are[lane * NS], &aim[lane * NS]);
                     }
                 }
             }
