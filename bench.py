@@ -43,12 +43,12 @@ WORKLOADS = {
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (256 CU x 2.4 GHz x 128 FLOP/clk)
 
-# HBM bytes per launch of k_direct_wave<2> (FP64) measured with rocprofv3 for the
+# HBM bytes per launch of k_direct_wave<2, true> (FP64) measured with rocprofv3 for the
 # current kernel revision: FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the factors
 # read off a 1 GiB device copy in the same runs
 # (profiles/k_direct_wave_fp64_level7_large_rule.md).  Re-measure after any
 # change to the kernel; other workloads were not measured.
-MEASURED_TRAFFIC = {"level7-large-rule": (3246995.5625 * 2.0 + 131072.0) * 1024.0}
+MEASURED_TRAFFIC = {"level7-large-rule": (3268320.3125 * 2.0 + 312408.25) * 1024.0}
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (256 CU x 2.4 GHz x 256 FLOP/clk)
 
 
@@ -56,23 +56,30 @@ def flops_per_pair(spec) -> float:
     """Algorithmic FLOPs (FMA = 2) per triangle-node pair of the
     wave-per-direction direct-sum kernel (16-node panels), counted from its
     source along the closed branch (the series branch replaces it for the few
-    pairs with a small phase spread).
+    pairs with a small phase spread); the count agrees with the FP64
+    operations of the compiled blocks.
 
     consumer, per node: 3 phase products (6 each) + closed-branch numerators
         (2 + 6) + complex multiply-accumulate (8)                      = 34
+    one sin/cos with its argument (turn-table reduction, degree-9/8
+        polynomials, rotation)                                          = 30
     producer, per (triangle, lane), once per batch of 8 triangles:
-        dot products, gaps, reciprocal (29) + (2 + PG) x 3 sin/cos (43
-        each) + their arguments (1 each) + scale factors and series
-        coefficients (70 per triangle, shared by its 8 lanes)
-    A lane owns 2*PG nodes and consumes 8 triangles per batch, so per pair:
-        34 + [29 + 3(2+PG)(43+1) + 70/8] / (8 * 2 PG).
+        dot products, gaps and the phase constants (20) + 3 (1 + PG)
+        sin/cos; with one wave per direction (16 panels, PG = 2) the second
+        panel's phase is a product instead: 3 (2 x 30 + 12) + 20       = 236
+    scale factors and series coefficients, once per triangle (shared by
+        its 8 lanes)                                                    = 62
+    running-sum merges: 2 * 2 PG adds per lane every 32 triangles.
+    A lane owns 2 PG nodes and consumes 8 triangles per batch, so per pair:
+        34 + (producer + 62 / 8) / (16 PG) + 1 / 16.
     The mixed form runs the same steps (FP32 sin/cos polynomials are shorter,
     but the count here is the FP64 one, used for both).
     """
     P = spec["n_panels"]
     PG = 2 if P % 16 == 0 else 1
-    producer = 29.0 + 3 * (2 + PG) * 44.0 + 70.0 / 8
-    return 34.0 + producer / (8 * 2 * PG)
+    one_wave = P == 8 * PG
+    producer = 3 * (2 * 30.0 + 12.0) + 20.0 if (one_wave and PG == 2) else 3 * (1 + PG) * 30.0 + 20.0
+    return 34.0 + (producer + 62.0 / 8) / (16 * PG) + 1.0 / 16
 
 
 def _progress(msg: str) -> None:

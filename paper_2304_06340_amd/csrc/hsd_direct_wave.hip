@@ -88,16 +88,17 @@ HSD_HD TriDir tri_dir(const TriRec &T, double J, double nx, double ny, double nz
 // Through n = 2 NC - 1: the first omitted term is below
 // (2 NC + 1) G^(2 NC) / (2 NC + 2)! relative to the leading 1/2, with
 // G = r (ac + bc) the scaled phase spread.
+// The scale factor rides along in H and the powers (H_0 = scale).
 template <int NC>
 HSD_HD void series_coefs(double ac, double bc, double scale, double ce[NC], double co[NC])
 {
-    double H = 1.0, pw = 1.0;
+    double H = scale, pw = scale;
     ce[0] = 0.5 * scale;
 #pragma unroll
     for (int n = 1; n <= 2 * NC - 1; ++n) {
         pw *= -ac;
         H = __builtin_fma(H, bc, pw);
-        const double hn = H * inv_factorial(n + 2) * scale;
+        const double hn = H * inv_factorial(n + 2);
         if (n & 1) co[n >> 1] = ((n >> 1) & 1) ? hn : -hn;
         else ce[n >> 1] = ((n >> 1) & 1) ? -hn : hn;
     }
@@ -116,9 +117,34 @@ HSD_HD void series_eval(const T ce[kNC64], const T co[kNC64], T r2, T &pe, T &po
     }
 }
 
+// Phase e^{-i h c} of the first panel's centre, held by the first lane of
+// each group of 8 producer lanes (one triangle) when the wave starts at
+// panel 0: broadcast within the group by an LDS swizzle (bit-mask mode, and
+// mask 0x18: every lane reads lane (lane & ~7) of its half-wave).  The host
+// emulation recomputes what that lane computed.
+HSD_HD cs64 group_first_phase(cs64 own, double hc, const cs64 *turn)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    (void)hc;
+    (void)turn;
+    cs64 r;
+    r.c = __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(own.c), 0x18),
+                           __builtin_amdgcn_ds_swizzle(__double2loint(own.c), 0x18));
+    r.s = __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(own.s), 0x18),
+                           __builtin_amdgcn_ds_swizzle(__double2loint(own.s), 0x18));
+    return r;
+#else
+    (void)own;
+    return sincos64_tab(hc, turn);
+#endif
+}
+
 // Producer, FP64: part j of a triangle's batch entry (the half-node phases
 // of node j and the centre phases of panels w0 + j PG .. w0 + j PG + PG-1).
-template <int PG>
+// ONE: the wave covers all panels of its direction (w0 = 0); the second
+// panel's phase is then the first one's times e^{-2 i h c}, the square of the
+// group's panel-0 phase, instead of another sin/cos.
+template <int PG, bool ONE>
 HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
                       const cs64 *turn, Scal64 *sc, cs64 Bk[3], cs64 Cp[PG][3])
 {
@@ -127,13 +153,25 @@ HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, i
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         Bk[c] = sincos64_tab(hx * fr[c], turn);
+        Cp[0][c] = sincos64_tab((double)(2 * (w0 + j * PG) + 1) * h * fr[c], turn);
+        if constexpr (ONE && PG > 1) {
+            const cs64 e1 = group_first_phase(Cp[0][c], h * fr[c], turn);
+            const cs64 step = pmul(e1, e1);
 #pragma unroll
-        for (int q = 0; q < PG; ++q)
-            Cp[q][c] = sincos64_tab((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c], turn);
+            for (int q = 1; q < PG; ++q) Cp[q][c] = pmul(Cp[q - 1][c], step);
+        } else {
+#pragma unroll
+            for (int q = 1; q < PG; ++q)
+                Cp[q][c] = sincos64_tab((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c], turn);
+        }
     }
     if (sc) {
-        sc->Ka = 2.0 * td.J * rcp64(td.ac) * td.iG;
-        sc->Kb = 2.0 * td.J * rcp64(td.bc) * td.iG;
+        // 1/ac and 1/bc from one reciprocal of ac bc (both gaps are floored
+        // at 1e-150, so the product stays a normal number)
+        const double rab = rcp64(td.ac * td.bc);
+        const double t = 2.0 * td.J * td.iG;
+        sc->Ka = t * (td.bc * rab);
+        sc->Kb = t * (td.ac * rab);
         sc->rthr = tau * td.iG;
         sc->pad = 0.0;
         series_coefs<kNC64>(td.ac, td.bc, td.J, sc->ce, sc->co);
@@ -196,8 +234,9 @@ HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, i
             Cp[j + kNH * q][c] = sincos32_acc((double)(2 * (w0 + j + kNH * q) + 1) * h * fr[c]);
     }
     if (sc) {
-        sc->Ka = (float)(2.0 * rcp64(td.ac) * td.iG);
-        sc->Kb = (float)(2.0 * rcp64(td.bc) * td.iG);
+        const double rab = rcp64(td.ac * td.bc);   // gaps floored at 1e-18
+        sc->Ka = (float)(2.0 * td.iG * (td.bc * rab));
+        sc->Kb = (float)(2.0 * td.iG * (td.ac * rab));
         sc->rthr = (float)(fmax(tau, kMixedTau) * td.iG);   // decides the branch only
         sc->pad = 0.0f;
         sc->J = td.J;
@@ -316,7 +355,7 @@ HSD_HD const TriRec *tri_at(const TriRec *A, int64_t nA, const TriRec *B, int64_
 // ---------------------------------------------------------------------------
 // kernel body: 4 waves per block, one direction (and panel window) per wave
 // ---------------------------------------------------------------------------
-template <int PG, int FORM>
+template <int PG, int FORM, bool ONE>
 __device__ __forceinline__ void direct_wave_body(
     const TriRec *__restrict__ A, int64_t nA, const TriRec *__restrict__ B, int64_t nB,
     const double *__restrict__ dirs, const double *__restrict__ hx_tab, int64_t d_begin, int64_t d_count,
@@ -370,8 +409,8 @@ __device__ __forceinline__ void direct_wave_body(
             const TriRec *rp = wv::tri_at(A, nA, B, gi, J);
             const TriDir td = tri_dir(*rp, J, nx, ny, nz, F64 ? kGapFloor : kGapFloor32);
             if constexpr (F64)
-                produce64<PG>(td, h, hx_tab, pj, w0, tau, turn, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
-                              &L.Cp[pt][pj * PG]);
+                produce64<PG, ONE>(td, h, hx_tab, pj, w0, tau, turn, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
+                                   &L.Cp[pt][pj * PG]);
             else
                 produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
                               L.Cp[pt]);
@@ -414,14 +453,14 @@ __device__ __forceinline__ void direct_wave_body(
 }
 
 // FP64 form: its LDS batch (10 KB per wave, 40 KB per block) allows 4
-// blocks per CU.
-template <int PG>
+// blocks per CU.  ONE: one wave per direction (the wave starts at panel 0).
+template <int PG, bool ONE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_direct_wave(
     const TriRec *__restrict__ A, int64_t nA, const TriRec *__restrict__ B, int64_t nB,
     const double *__restrict__ dirs, const double *__restrict__ hx_tab, int64_t d_begin, int64_t d_count,
     int P, double h, double tau, int64_t N, double2 *__restrict__ partial)
 {
-    direct_wave_body<PG, HSD_FORM_FP64>(A, nA, B, nB, dirs, hx_tab, d_begin, d_count, P, h, tau, N, partial);
+    direct_wave_body<PG, HSD_FORM_FP64, ONE>(A, nA, B, nB, dirs, hx_tab, d_begin, d_count, P, h, tau, N, partial);
 }
 
 // Mixed form: its 7 KB of LDS per wave leave the registers as the limit;
@@ -433,7 +472,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     const double *__restrict__ dirs, const double *__restrict__ hx_tab, int64_t d_begin, int64_t d_count,
     int P, double h, double tau, int64_t N, double2 *__restrict__ partial)
 {
-    direct_wave_body<PG, HSD_FORM_MIXED>(A, nA, B, nB, dirs, hx_tab, d_begin, d_count, P, h, tau, N, partial);
+    direct_wave_body<PG, HSD_FORM_MIXED, false>(A, nA, B, nB, dirs, hx_tab, d_begin, d_count, P, h, tau, N, partial);
 }
 
 bool wave_kernel_applies(const hsd_rule *rule)
@@ -462,8 +501,14 @@ static hsd_status launch_wave_pg(hipStream_t st, const MeshPair &mp, const hsd_r
         return HSD_EINVAL;
     }
     dim3 grid((unsigned)blocks, (unsigned)K), block(256);
-    if (form == HSD_FORM_FP64)
-        hipLaunchKernelGGL((k_direct_wave<PG>), grid, block, 0, st, mp.A, mp.nA, mp.B, mp.nB,
+    // the single-wave variant differs only where a lane holds two panels
+    constexpr bool kOne = PG > 1;
+    if (form == HSD_FORM_FP64 && kOne && wpd == 1)
+        hipLaunchKernelGGL((k_direct_wave<PG, kOne>), grid, block, 0, st, mp.A, mp.nA, mp.B, mp.nB,
+                           rule->d_dirs.as<const double>(), rule->d_hx.as<const double>(), d_begin, d_count,
+                           rule->sp.P, rule->sp.h, tau, rule->n_nodes, partial);
+    else if (form == HSD_FORM_FP64)
+        hipLaunchKernelGGL((k_direct_wave<PG, false>), grid, block, 0, st, mp.A, mp.nA, mp.B, mp.nB,
                            rule->d_dirs.as<const double>(), rule->d_hx.as<const double>(), d_begin, d_count,
                            rule->sp.P, rule->sp.h, tau, rule->n_nodes, partial);
     else
@@ -509,8 +554,12 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
                 const TriDir td = tri_dir(*rp, J, nx, ny, nz, F64 ? kGapFloor : kGapFloor32);
                 if (F64) {
                     auto &L = b64[0];
-                    produce64<PG>(td, h, hx_tab, pj, w0, tau, turn, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
-                                  &L.Cp[pt][pj * PG]);
+                    if (wpd == 1)
+                        produce64<PG, true>(td, h, hx_tab, pj, w0, tau, turn, pj == 0 ? &L.sc[pt] : nullptr,
+                                            L.Bk[pt][pj], &L.Cp[pt][pj * PG]);
+                    else
+                        produce64<PG, false>(td, h, hx_tab, pj, w0, tau, turn, pj == 0 ? &L.sc[pt] : nullptr,
+                                             L.Bk[pt][pj], &L.Cp[pt][pj * PG]);
                 } else {
                     auto &L = b32[0];
                     produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
