@@ -16,11 +16,22 @@
 
 namespace hsd {
 
-constexpr int kFftThreads = 256;
+constexpr int kFftThreads = 512;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b)
 {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// a / d for 0 <= a < 2^22 and 1 <= d < 2^12, given rd = 1.0f / d: the FP32
+// product is within a relative 2^-23 of a / d, so its truncation is the
+// quotient or one off, which the two corrections remove.
+__device__ __forceinline__ int qdiv(int a, int d, float rd)
+{
+    int q = (int)((float)a * rd);
+    q += (q + 1) * d <= a ? 1 : 0;
+    q -= q * d > a ? 1 : 0;
+    return q;
 }
 
 constexpr int kFftMaxElems = 4374;   // complex values per block tile (68 KB of LDS: two blocks per CU)
@@ -28,6 +39,9 @@ constexpr int kFftMaxElems = 4374;   // complex values per block tile (68 KB of 
 // One Stockham stage of radix R on Bt lines of length n in LDS: every
 // thread first gathers (and twiddles) the inputs of all its butterflies into
 // registers, the block synchronises, then the outputs are written in place.
+// A butterfly reads one twiddle w = exp(-2 pi i k / (Ns R)) from the table
+// (all of a thread's reads issued before any is used) and forms w^2, w^3 by
+// products; indices are divided through FP32 reciprocals (qdiv).
 template <int R>
 __device__ void stockham_stage(double2 *buf, int n, int Bt, int Ns, const double2 *__restrict__ tw)
 {
@@ -35,19 +49,33 @@ __device__ void stockham_stage(double2 *buf, int n, int Bt, int Ns, const double
     const int nb = n / R;              // butterflies per line
     const int total = nb * Bt;
     const int twstep = n / (Ns * R);   // exp(-2 pi i / (Ns R)) = tw[twstep]
+    const float rnb = 1.0f / (float)nb, rns = 1.0f / (float)Ns;
+    int jj[kMaxBf], ll[kMaxBf], kk[kMaxBf];
+    double2 w1[kMaxBf];
+#pragma unroll
+    for (int b = 0; b < kMaxBf; ++b) {
+        const int idx = b * kFftThreads + (int)threadIdx.x;
+        const int line = qdiv(idx, nb, rnb);
+        const int j = idx - line * nb;
+        const int k = j - qdiv(j, Ns, rns) * Ns;
+        ll[b] = line;
+        jj[b] = j;
+        kk[b] = k;
+        w1[b] = tw[idx < total ? k * twstep : 0];
+    }
     double2 x[kMaxBf][R];
 #pragma unroll
     for (int b = 0; b < kMaxBf; ++b) {
         const int idx = b * kFftThreads + (int)threadIdx.x;
         if (idx < total) {
-            const int line = idx / nb;
-            const int j = idx - line * nb;
-            const double2 *L = buf + (size_t)line * n;
-            const int k = j % Ns;
+            const double2 *L = buf + (size_t)ll[b] * n;
+            const double2 w2 = cmul(w1[b], w1[b]);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                double2 a = L[j + r * nb];
-                if (r > 0) a = cmul(a, tw[r * k * twstep]);
+                double2 a = L[jj[b] + r * nb];
+                if (r == 1) a = cmul(a, w1[b]);
+                if (r == 2) a = cmul(a, w2);
+                if (r == 3) a = cmul(a, cmul(w2, w1[b]));
                 x[b][r] = a;
             }
         }
@@ -57,8 +85,8 @@ __device__ void stockham_stage(double2 *buf, int n, int Bt, int Ns, const double
     for (int b = 0; b < kMaxBf; ++b) {
         const int idx = b * kFftThreads + (int)threadIdx.x;
         if (idx < total) {
-            const int line = idx / nb;
-            const int j = idx - line * nb;
+            const int line = ll[b];
+            const int j = jj[b];
             const double2 *xi = x[b];
             double2 y[R];
             if (R == 2) {
@@ -86,8 +114,8 @@ __device__ void stockham_stage(double2 *buf, int n, int Bt, int Ns, const double
                 y[3] = make_double2(a1.x - b1.y, a1.y + b1.x);
             }
             double2 *L = buf + (size_t)line * n;
-            const int k = j % Ns;
-            const int obase = (j / Ns) * Ns * R + k;
+            const int k = kk[b];
+            const int obase = (j - k) * R + k;
 #pragma unroll
             for (int q = 0; q < R; ++q) L[obase + q * Ns] = y[q];
         }
@@ -103,7 +131,7 @@ __device__ __forceinline__ int64_t unprune(int64_t c, int e, int gap) { return c
 // data[o * so + i * si + e * se]; blockIdx.x covers Bt consecutive compact
 // inner indices for one compact outer index blockIdx.y, each mapped by
 // unprune (e_i, gap_i) and (e_o, gap_o).
-__global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *__restrict__ data, int n, int Bt, int64_t se,
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_axis(double2 *__restrict__ data, int n, int Bt, int64_t se,
                                                           int64_t si, int64_t so, int64_t n_inner,
                                                           const double2 *__restrict__ tw, const int *__restrict__ plan,
                                                           int n_stages, int e_i, int gap_i, int e_o, int gap_o)
@@ -114,12 +142,27 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *__restrict__ 
     const int nl = (int)((n_inner - i0) < Bt ? (n_inner - i0) : Bt);
     double2 *base = data + o * so;
     const int total = nl * n;
-    // load
-    for (int idx = threadIdx.x; idx < total; idx += kFftThreads) {
-        int line, e;
-        if (se == 1) { line = idx / n; e = idx - line * n; }
-        else { e = idx / nl; line = idx - e * nl; }
-        lds[(size_t)line * n + e] = base[unprune(i0 + line, e_i, gap_i) * si + (int64_t)e * se];
+    const float rn = 1.0f / (float)n, rnl = 1.0f / (float)nl;
+    // load: batches of kLoadBatch independent global reads per thread, all
+    // issued before their LDS writes, so that they overlap
+    constexpr int kLoadBatch = 8;
+    for (int idx0 = threadIdx.x; idx0 < total; idx0 += kLoadBatch * kFftThreads) {
+        double2 v[kLoadBatch];
+        int slot[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            // past the tile's end: read the tile's last element again (in
+            // bounds) and write that same value back to its own LDS slot, so
+            // that neither the reads nor the writes need a branch
+            const int idx = min(idx0 + u * kFftThreads, total - 1);
+            int line, e;
+            if (se == 1) { line = qdiv(idx, n, rn); e = idx - line * n; }
+            else { e = qdiv(idx, nl, rnl); line = idx - e * nl; }
+            slot[u] = line * n + e;
+            v[u] = base[unprune(i0 + line, e_i, gap_i) * si + (int64_t)e * se];
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) lds[slot[u]] = v[u];
     }
     __syncthreads();
     int Ns = 1;
@@ -133,8 +176,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_axis(double2 *__restrict__ 
     // store
     for (int idx = threadIdx.x; idx < total; idx += kFftThreads) {
         int line, e;
-        if (se == 1) { line = idx / n; e = idx - line * n; }
-        else { e = idx / nl; line = idx - e * nl; }
+        if (se == 1) { line = qdiv(idx, n, rn); e = idx - line * n; }
+        else { e = qdiv(idx, nl, rnl); line = idx - e * nl; }
         base[unprune(i0 + line, e_i, gap_i) * si + (int64_t)e * se] = lds[(size_t)line * n + e];
     }
 }
