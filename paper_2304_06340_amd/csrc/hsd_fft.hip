@@ -130,21 +130,32 @@ __device__ __forceinline__ int64_t unprune(int64_t c, int e, int gap) { return c
 // Batched 1-D FFTs along one axis.  Line (o, i) element e lives at
 // data[o * so + i * si + e * se]; blockIdx.x covers Bt consecutive compact
 // inner indices for one compact outer index blockIdx.y, each mapped by
-// unprune (e_i, gap_i) and (e_o, gap_o).
-__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_axis(double2 *__restrict__ data, int n, int Bt, int64_t se,
-                                                          int64_t si, int64_t so, int64_t n_inner,
-                                                          const double2 *__restrict__ tw, const int *__restrict__ plan,
-                                                          int n_stages, int e_i, int gap_i, int e_o, int gap_o)
+// unprune (e_i, gap_i) and (e_o, gap_o).  Along the line only the elements
+// of the input band (e_r, gap_r) are read (the others are zero and are
+// filled in LDS) and only those of the output band (e_w, gap_w) written.
+__global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_fft_axis(
+    double2 *__restrict__ data, int n, int Bt, int64_t se, int64_t si, int64_t so, int64_t n_inner,
+    const double2 *__restrict__ tw, const int *__restrict__ plan, int n_stages, int e_i, int gap_i, int e_o,
+    int gap_o, int e_r, int gap_r, int e_w, int gap_w)
 {
     extern __shared__ double2 lds[];
     const int64_t i0 = (int64_t)blockIdx.x * Bt;
     const int64_t o = unprune(blockIdx.y, e_o, gap_o);
     const int nl = (int)((n_inner - i0) < Bt ? (n_inner - i0) : Bt);
     double2 *base = data + o * so;
-    const int total = nl * n;
-    const float rn = 1.0f / (float)n, rnl = 1.0f / (float)nl;
+    const int nr = n - gap_r, nw = n - gap_w;   // elements read / written per line
+    const float rnr = 1.0f / (float)nr, rnw = 1.0f / (float)nw, rnl = 1.0f / (float)nl;
+    // zeros of the input band's gap
+    if (gap_r > 0) {
+        const float rg = 1.0f / (float)gap_r;
+        for (int idx = threadIdx.x; idx < nl * gap_r; idx += kFftThreads) {
+            const int line = qdiv(idx, gap_r, rg);
+            lds[line * n + e_r + (idx - line * gap_r)] = make_double2(0.0, 0.0);
+        }
+    }
     // load: batches of kLoadBatch independent global reads per thread, all
     // issued before their LDS writes, so that they overlap
+    const int total = nl * nr;
     constexpr int kLoadBatch = 8;
     for (int idx0 = threadIdx.x; idx0 < total; idx0 += kLoadBatch * kFftThreads) {
         double2 v[kLoadBatch];
@@ -155,9 +166,10 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4))
             // bounds) and write that same value back to its own LDS slot, so
             // that neither the reads nor the writes need a branch
             const int idx = min(idx0 + u * kFftThreads, total - 1);
-            int line, e;
-            if (se == 1) { line = qdiv(idx, n, rn); e = idx - line * n; }
-            else { e = qdiv(idx, nl, rnl); line = idx - e * nl; }
+            int line, c;
+            if (se == 1) { line = qdiv(idx, nr, rnr); c = idx - line * nr; }
+            else { c = qdiv(idx, nl, rnl); line = idx - c * nl; }
+            const int e = (int)unprune(c, e_r, gap_r);
             slot[u] = line * n + e;
             v[u] = base[unprune(i0 + line, e_i, gap_i) * si + (int64_t)e * se];
         }
@@ -173,11 +185,12 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4))
         else stockham_stage<2>(lds, n, nl, Ns, tw);
         Ns *= R;
     }
-    // store
-    for (int idx = threadIdx.x; idx < total; idx += kFftThreads) {
-        int line, e;
-        if (se == 1) { line = qdiv(idx, n, rn); e = idx - line * n; }
-        else { e = qdiv(idx, nl, rnl); line = idx - e * nl; }
+    // store the output band
+    for (int idx = threadIdx.x; idx < nl * nw; idx += kFftThreads) {
+        int line, c;
+        if (se == 1) { line = qdiv(idx, nw, rnw); c = idx - line * nw; }
+        else { c = qdiv(idx, nl, rnl); line = idx - c * nl; }
+        const int e = (int)unprune(c, e_w, gap_w);
         base[unprune(i0 + line, e_i, gap_i) * si + (int64_t)e * se] = lds[(size_t)line * n + e];
     }
 }
@@ -244,7 +257,7 @@ hsd_status fft3d_forward(hipStream_t st, const FftPlan &p, double2 *data, int e_
         dim3 grid((unsigned)((in.cnt + bt - 1) / bt), (unsigned)in.cnt);
         hipLaunchKernelGGL(k_fft_axis, grid, dim3(kFftThreads), lds, st, data, n, bt, (int64_t)1, (int64_t)n,
                            (int64_t)n * n, (int64_t)in.cnt, p.tw.as<const double2>(), p.plan.as<const int>(), ns,
-                           in.e, in.gap, in.e, in.gap);
+                           in.e, in.gap, in.e, in.gap, in.e, in.gap, out.e, out.gap);
         HSD_HIP_TRY(hipGetLastError());
     }
     // axis y: element stride n; inner = z (wanted outputs), outer = x (input)
@@ -252,7 +265,7 @@ hsd_status fft3d_forward(hipStream_t st, const FftPlan &p, double2 *data, int e_
         dim3 grid((unsigned)((out.cnt + bt - 1) / bt), (unsigned)in.cnt);
         hipLaunchKernelGGL(k_fft_axis, grid, dim3(kFftThreads), lds, st, data, n, bt, (int64_t)n, (int64_t)1,
                            (int64_t)n * n, (int64_t)out.cnt, p.tw.as<const double2>(), p.plan.as<const int>(), ns,
-                           out.e, out.gap, in.e, in.gap);
+                           out.e, out.gap, in.e, in.gap, in.e, in.gap, out.e, out.gap);
         HSD_HIP_TRY(hipGetLastError());
     }
     // axis x: element stride n^2; inner = z, outer = y (wanted outputs)
@@ -260,7 +273,7 @@ hsd_status fft3d_forward(hipStream_t st, const FftPlan &p, double2 *data, int e_
         dim3 grid((unsigned)((out.cnt + bt - 1) / bt), (unsigned)out.cnt);
         hipLaunchKernelGGL(k_fft_axis, grid, dim3(kFftThreads), lds, st, data, n, bt, (int64_t)n * n, (int64_t)1,
                            (int64_t)n, (int64_t)out.cnt, p.tw.as<const double2>(), p.plan.as<const int>(), ns,
-                           out.e, out.gap, out.e, out.gap);
+                           out.e, out.gap, out.e, out.gap, in.e, in.gap, out.e, out.gap);
         HSD_HIP_TRY(hipGetLastError());
     }
     return HSD_OK;
@@ -272,8 +285,8 @@ extern "C" {
 
 // Test hook (not part of the public ABI): forward 3-D FFT of a host cube
 // [n][n][n] of interleaved complex values, in place, on `ctx`'s device;
-// e_in, e_out as for fft3d_forward (with e_out > 0 only outputs with y and z
-// in the wrapped centred cube of half-extent e_out are defined).
+// e_in, e_out as for fft3d_forward (with e_out > 0 only outputs in the
+// wrapped centred cube of half-extent e_out are defined).
 int hsd__test_fft3d_pruned(hsd_ctx *ctx, double *host_data, int n, int e_in, int e_out)
 {
     using namespace hsd;

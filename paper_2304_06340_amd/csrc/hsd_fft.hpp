@@ -20,11 +20,12 @@ int fft_next_size(int n);
 // In-place forward transform of data[n][n][n] on stream st.  Pruning (a
 // half-extent e > 0 names the wrapped centred cube m < e or m >= n - e of
 // every axis; e = 0 or 2e >= n means the whole axis):
-//  * e_in: the input is zero outside that cube, so lines of zeros are
-//    skipped;
-//  * e_out: only outputs with y and z inside that cube are wanted (all x);
-//    the lines that cannot reach them are skipped and the rest of the array
-//    is left undefined.
+//  * e_in: the input is zero outside that cube (its values there are not
+//    read), so lines of zeros are skipped and each line is read only in the
+//    band;
+//  * e_out: only outputs inside that cube are wanted; the lines that cannot
+//    reach them are skipped, each line is written only in the band, and the
+//    rest of the array is left undefined.
 hsd_status fft3d_forward(hipStream_t st, const FftPlan &p, double2 *data, int e_in = 0, int e_out = 0);
 
 } // namespace hsd

@@ -345,19 +345,22 @@ __global__ __launch_bounds__(64) void k_tile_reduce(const double *__restrict__ t
 }
 
 // --------------------------------------------------------------------------
-// 3. pre-deconvolve + zero-pad into the fine grid (index m <-> l' = m or m - n2)
+// 3. pre-deconvolve into the fine grid (index m <-> l' = m or m - n2), over
+//    the wrapped band m < e, m >= n2 - e of every axis only (cnt = 2 e
+//    compact indices per axis, gap = n2 - 2 e; e <= n1 / 2): the fine grid is
+//    zero outside it, and the FFT neither reads nor needs those values
 // --------------------------------------------------------------------------
 __global__ void k_predeconv(const double *__restrict__ grid, int n1, const double *__restrict__ hinv,
-                            int n2, double2 *__restrict__ fine)
+                            int n2, int cnt, int e, int gap, double2 *__restrict__ fine)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t tot = (int64_t)n2 * n2 * n2;
+    const int64_t tot = (int64_t)cnt * cnt * cnt;
     if (g >= tot) return;
-    const int mz = (int)(g % n2), my = (int)((g / n2) % n2), mx = (int)(g / ((int64_t)n2 * n2));
-    const int m[3] = {mx, my, mz};
-    int l[3];
+    const int c[3] = {(int)(g / ((int64_t)cnt * cnt)), (int)((g / cnt) % cnt), (int)(g % cnt)};
+    int m[3], l[3];
     bool in = true;
     for (int d = 0; d < 3; ++d) {
+        m[d] = c[d] < e ? c[d] : c[d] + gap;
         const int lp = m[d] < n2 / 2 ? m[d] : m[d] - n2;   // signed frequency index
         l[d] = lp + n1 / 2;
         in = in && (l[d] >= 0 && l[d] < n1);
@@ -367,7 +370,7 @@ __global__ void k_predeconv(const double *__restrict__ grid, int n1, const doubl
         const int64_t cell = ((int64_t)l[0] * n1 + l[1]) * n1 + l[2];
         v = grid[cell] * (hinv[l[0]] * hinv[l[1]] * hinv[l[2]]);
     }
-    fine[g] = make_double2(v, 0.0);
+    fine[((int64_t)m[0] * n2 + m[1]) * n2 + m[2]] = make_double2(v, 0.0);
 }
 
 // --------------------------------------------------------------------------
@@ -756,14 +759,22 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)ntiles), dim3(64), 0, st, sc.tilebuf.as<const double>(),
                        sc.tstart.as<const int>(), nbx, n1, sc.grid1.as<double>());
     HSD_HIP_TRY(hipGetLastError());
-    const int64_t tot2 = (int64_t)n2 * n2 * n2;
-    hipLaunchKernelGGL(k_predeconv, dim3((unsigned)((tot2 + 255) / 256)), dim3(256), 0, st, sc.grid1.as<const double>(),
-                       n1, sc.hinv.as<const double>(), n2, sc.fine.as<double2>());
-    HSD_HIP_TRY(hipGetLastError());
     // the spread grid is zero beyond |l - n1/2| > X / h1 + w / 2 (all points
     // lie within X of the origin), so the fine grid is zero outside the
-    // wrapped indices m < e, m >= n2 - e: the FFT skips those lines
+    // wrapped indices m < e, m >= n2 - e: only that band is written, and the
+    // FFT skips the other lines and reads each line only in the band
     const int e_occ = std::min(n1 / 2, (int)std::floor(X / h1 + 0.5 * w) + 2);
+    {
+        // the band convention of fft3d_forward: e <= 0 or 2 e >= n2 is the whole axis
+        const bool band = e_occ > 0 && 2 * e_occ < n2;
+        const int cnt = band ? 2 * e_occ : n2;
+        const int e = band ? e_occ : n2, gap = n2 - cnt;
+        const int64_t tot = (int64_t)cnt * cnt * cnt;
+        hipLaunchKernelGGL(k_predeconv, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                           sc.grid1.as<const double>(), n1, sc.hinv.as<const double>(), n2, cnt, e, gap,
+                           sc.fine.as<double2>());
+        HSD_HIP_TRY(hipGetLastError());
+    }
     // and only the indices the read-out touches are wanted: the lattice
     // indices |k| <= M / 2, or the interpolation stencils around the scaled
     // targets |u| <= S n2 h1 / (2 pi) (w points from ceil(u - w/2))
