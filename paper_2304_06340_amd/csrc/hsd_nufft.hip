@@ -419,15 +419,33 @@ __global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine
                                                 const int4 *__restrict__ items, int H, int nt1,
                                                 double2 *__restrict__ out)
 {
-    constexpr int TS = interp_tile<W>(), B = TS + W - 1;
-    __shared__ double2 box[B * B * B];
+    constexpr int TS = interp_tile<W>(), B = TS + W - 1, B3 = B * B * B;
+    __shared__ double2 box[B3];
+    __shared__ int wrapped[3][B];        // periodic grid index of each box coordinate
     const int4 it = items[blockIdx.x];   // (tile, first target, end, 0) in the sorted order
     const int tile = it.x;
     const int o[3] = {(tile / (nt1 * nt1)) * TS - H, ((tile / nt1) % nt1) * TS - H, (tile % nt1) * TS - H};
-    for (int e = threadIdx.x; e < B * B * B; e += blockDim.x) {
-        const int bz = e % B, by = (e / B) % B, bx = e / (B * B);
-        box[e] = fine[((int64_t)wrap_index(o[0] + bx, n2) * n2 + wrap_index(o[1] + by, n2)) * n2 +
-                      wrap_index(o[2] + bz, n2)];
+    if (threadIdx.x < 3 * B) {
+        const int a = threadIdx.x / B, bb = threadIdx.x - a * B;
+        wrapped[a][bb] = wrap_index(o[a] + bb, n2);
+    }
+    __syncthreads();
+    // stage the box: batches of 8 independent reads per thread issued before
+    // their LDS writes; past the end a thread reads the box's last element
+    // again and writes that same value back to its own slot (no branches)
+    constexpr int kBatch = 8;
+    for (int e0 = threadIdx.x; e0 < B3; e0 += kBatch * (int)blockDim.x) {
+        double2 v[kBatch];
+        int slot[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = min(e0 + u * (int)blockDim.x, B3 - 1);
+            const int bz = e % B, by = (e / B) % B, bx = e / (B * B);
+            slot[u] = e;
+            v[u] = fine[((int64_t)wrapped[0][bx] * n2 + wrapped[1][by]) * n2 + wrapped[2][bz]];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) box[slot[u]] = v[u];
     }
     __syncthreads();
     const double half_w = 0.5 * W;
@@ -439,8 +457,11 @@ __global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine
         const int k = order[t];
         const int d = k / n_rad;
         const double r = radii[k - d * n_rad];
-        double wt[3][W];
+        // kernel weights per axis in registers (all loops over them unrolled:
+        // an array indexed by a loop counter would live in scratch memory)
+        double wx[W], wy[W], wz[W];
         int b[3];
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
             const double u = r * dirs[3 * d + a] * scale;
             const int lo = (int)ceil(u - half_w);
@@ -448,20 +469,23 @@ __global__ __launch_bounds__(256) void k_interp(const double2 *__restrict__ fine
             // only keeps every LDS read inside the box
             const int bb = lo - o[a];
             b[a] = bb < 0 ? 0 : (bb > TS - 1 ? TS - 1 : bb);
+            double *wa = a == 0 ? wx : (a == 1 ? wy : wz);
 #pragma unroll
-            for (int i = 0; i < W; ++i) wt[a][i] = es_eval(((double)(lo + i) - u) * iw, beta);
+            for (int i = 0; i < W; ++i) wa[i] = es_eval(((double)(lo + i) - u) * iw, beta);
         }
         double re = 0.0, im = 0.0;
+#pragma unroll
         for (int i = 0; i < W; ++i) {
+#pragma unroll
             for (int j = 0; j < W; ++j) {
-                const double wxy = wt[0][i] * wt[1][j];
+                const double wxy = wx[i] * wy[j];
                 const double2 *row = box + ((b[0] + i) * B + (b[1] + j)) * B + b[2];
                 double sre = 0.0, sim = 0.0;
 #pragma unroll
                 for (int l = 0; l < W; ++l) {
                     const double2 v = row[l];
-                    sre = __builtin_fma(v.x, wt[2][l], sre);
-                    sim = __builtin_fma(v.y, wt[2][l], sim);
+                    sre = __builtin_fma(v.x, wz[l], sre);
+                    sim = __builtin_fma(v.y, wz[l], sim);
                 }
                 re = __builtin_fma(sre, wxy, re);
                 im = __builtin_fma(sim, wxy, im);
