@@ -4,7 +4,7 @@
 // One kernel per axis.  A block loads Bt whole 1-D lines of the axis into
 // LDS (for the strided axes the Bt lines are consecutive in the contiguous
 // dimension, so every global access is a coalesced run of Bt complex
-// values), runs a Stockham autosort FFT in LDS (radix 4, 3 and 2 stages;
+// values), runs a Stockham autosort FFT in LDS (radix 9, 4, 3 and 2 stages;
 // each stage reads its inputs to registers, synchronises, and writes its
 // outputs in place), and writes the lines back.  Twiddles come from a table
 // exp(-2 pi i k / n), k < n, built on the host in FP64.
@@ -36,12 +36,29 @@ __device__ __forceinline__ int qdiv(int a, int d, float rd)
 
 constexpr int kFftMaxElems = 4374;   // complex values per block tile (68 KB of LDS: two blocks per CU)
 
+// 3-point DFT, forward sign: y_q = sum_r x_r exp(-2 pi i r q / 3)
+__device__ __forceinline__ void dft3(double2 x0, double2 x1, double2 x2, double2 &y0, double2 &y1, double2 &y2)
+{
+    // exp(-2 pi i / 3) = -1/2 - i sqrt(3)/2
+    const double c = -0.5, s = 0.86602540378443864676;
+    const double2 t = make_double2(x1.x + x2.x, x1.y + x2.y);
+    const double2 d = make_double2(x1.x - x2.x, x1.y - x2.y);
+    y0 = make_double2(x0.x + t.x, x0.y + t.y);
+    const double2 m = make_double2(x0.x + c * t.x, x0.y + c * t.y);
+    // -i s d = (s d.y, -s d.x)
+    y1 = make_double2(m.x + s * d.y, m.y - s * d.x);
+    y2 = make_double2(m.x - s * d.y, m.y + s * d.x);
+}
+
 // One Stockham stage of radix R on Bt lines of length n in LDS: every
 // thread first gathers (and twiddles) the inputs of all its butterflies into
 // registers, the block synchronises, then the outputs are written in place.
 // A butterfly reads one twiddle w = exp(-2 pi i k / (Ns R)) from the table
-// (all of a thread's reads issued before any is used) and forms w^2, w^3 by
-// products; indices are divided through FP32 reciprocals (qdiv).
+// (all of a thread's reads issued before any is used) and forms its powers
+// by products; indices are divided through FP32 reciprocals (qdiv).  Radix 9
+// is a 3 x 3 decomposition in registers (inner 3-point DFTs over r2 of
+// r = r1 + 3 r2, twiddles exp(-2 pi i r1 q1 / 9), outer 3-point DFTs over
+// r1), so that a 729-point line takes three LDS passes instead of six.
 template <int R>
 __device__ void stockham_stage(double2 *buf, int n, int Bt, int Ns, const double2 *__restrict__ tw)
 {
@@ -69,13 +86,12 @@ __device__ void stockham_stage(double2 *buf, int n, int Bt, int Ns, const double
         const int idx = b * kFftThreads + (int)threadIdx.x;
         if (idx < total) {
             const double2 *L = buf + (size_t)ll[b] * n;
-            const double2 w2 = cmul(w1[b], w1[b]);
+            double2 wp = w1[b];   // w^r
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 double2 a = L[jj[b] + r * nb];
-                if (r == 1) a = cmul(a, w1[b]);
-                if (r == 2) a = cmul(a, w2);
-                if (r == 3) a = cmul(a, cmul(w2, w1[b]));
+                if (r >= 1) a = cmul(a, wp);
+                if (r >= 1 && r + 1 < R) wp = cmul(wp, w1[b]);
                 x[b][r] = a;
             }
         }
@@ -93,15 +109,21 @@ __device__ void stockham_stage(double2 *buf, int n, int Bt, int Ns, const double
                 y[0] = make_double2(xi[0].x + xi[1].x, xi[0].y + xi[1].y);
                 y[1] = make_double2(xi[0].x - xi[1].x, xi[0].y - xi[1].y);
             } else if (R == 3) {
-                // exp(-2 pi i / 3) = -1/2 - i sqrt(3)/2
-                const double c = -0.5, s = 0.86602540378443864676;
-                const double2 t = make_double2(xi[1].x + xi[2].x, xi[1].y + xi[2].y);
-                const double2 d = make_double2(xi[1].x - xi[2].x, xi[1].y - xi[2].y);
-                y[0] = make_double2(xi[0].x + t.x, xi[0].y + t.y);
-                const double2 m = make_double2(xi[0].x + c * t.x, xi[0].y + c * t.y);
-                // -i s d = (s d.y, -s d.x)
-                y[1] = make_double2(m.x + s * d.y, m.y - s * d.x);
-                y[2] = make_double2(m.x - s * d.y, m.y + s * d.x);
+                dft3(xi[0], xi[1], xi[2], y[0], y[1], y[2]);
+            } else if (R == 9) {
+                // exp(-2 pi i k / 9) for k = 1, 2, 4
+                const double2 w9_1 = make_double2(0.766044443118978035202, -0.642787609686539326323);
+                const double2 w9_2 = make_double2(0.173648177666930348852, -0.984807753012208059367);
+                const double2 w9_4 = make_double2(-0.939692620785908384054, -0.342020143325668733044);
+                double2 z[3][3];   // z[r1][q1]
+#pragma unroll
+                for (int r1 = 0; r1 < 3; ++r1) dft3(xi[r1], xi[r1 + 3], xi[r1 + 6], z[r1][0], z[r1][1], z[r1][2]);
+                z[1][1] = cmul(z[1][1], w9_1);
+                z[1][2] = cmul(z[1][2], w9_2);
+                z[2][1] = cmul(z[2][1], w9_2);
+                z[2][2] = cmul(z[2][2], w9_4);
+#pragma unroll
+                for (int q1 = 0; q1 < 3; ++q1) dft3(z[0][q1], z[1][q1], z[2][q1], y[q1], y[q1 + 3], y[q1 + 6]);
             } else {   // R == 4
                 const double2 a0 = make_double2(xi[0].x + xi[2].x, xi[0].y + xi[2].y);
                 const double2 a1 = make_double2(xi[0].x - xi[2].x, xi[0].y - xi[2].y);
@@ -180,7 +202,8 @@ __global__ __launch_bounds__(kFftThreads) __attribute__((amdgpu_waves_per_eu(4))
     int Ns = 1;
     for (int s = 0; s < n_stages; ++s) {
         const int R = plan[s];
-        if (R == 4) stockham_stage<4>(lds, n, nl, Ns, tw);
+        if (R == 9) stockham_stage<9>(lds, n, nl, Ns, tw);
+        else if (R == 4) stockham_stage<4>(lds, n, nl, Ns, tw);
         else if (R == 3) stockham_stage<3>(lds, n, nl, Ns, tw);
         else stockham_stage<2>(lds, n, nl, Ns, tw);
         Ns *= R;
@@ -218,6 +241,7 @@ hsd_status FftPlan::init(hsd_ctx *ctx, int n_)
     n = n_;
     std::vector<int> st;
     int m = n;
+    while (m % 9 == 0) { st.push_back(9); m /= 9; }
     while (m % 4 == 0) { st.push_back(4); m /= 4; }
     while (m % 3 == 0) { st.push_back(3); m /= 3; }
     while (m % 2 == 0) { st.push_back(2); m /= 2; }

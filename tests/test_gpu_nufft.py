@@ -14,7 +14,7 @@ from hsd_inputs import icosphere, perturb_radial, random_rotation, rotate
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("n", [8, 12, 24, 27, 48, 64, 96, 192])
+@pytest.mark.parametrize("n", [8, 12, 24, 27, 48, 64, 81, 96, 192, 243])
 def test_fft3d_against_numpy(hsd_ctx, n):
     L = hsd_ctx._lib
     f = L.hsd__test_fft3d
