@@ -40,6 +40,7 @@ namespace hsd {
 constexpr int kBin = 8;            // grid cells per bin / spread tile edge
 static_assert(kBin == 8, "the spread kernel splits value indices by shifts");
 constexpr int kChunk = 64;         // points staged in LDS per spread step
+constexpr double kKeepMargin = 1e-6; // grid units, see k_spread
 constexpr int kMaxW = 16;          // largest kernel width supported
 
 struct EsKernel {
@@ -255,10 +256,16 @@ __global__ __launch_bounds__(64) void k_spread(const double4 *__restrict__ spts,
                         g[1] = __builtin_fma(p.y, ih1, half);
                         g[2] = __builtin_fma(p.z, ih1, half);
                         wv = p.w;
+                        // the point reaches a grid line org + i of the tile
+                        // (|org + i - g| < w/2 on every axis) iff
+                        // org - w/2 < g < org + kBin - 1 + w/2; beyond that its
+                        // kernel values on the tile are exactly 0.  The margin
+                        // (far above the rounding of g) only keeps points whose
+                        // values there are 0 anyway.
                         keep = true;
                         for (int d = 0; d < 3; ++d)
-                            keep = keep && g[d] > (double)org[d] - half_w - 1.0 &&
-                                   g[d] < (double)(org[d] + kBin - 1) + half_w + 1.0;
+                            keep = keep && g[d] > (double)org[d] - half_w - kKeepMargin &&
+                                   g[d] < (double)(org[d] + kBin - 1) + half_w + kKeepMargin;
                     }
                     const unsigned long long m = __ballot(keep);
                     const int nk = __popcll(m);
