@@ -106,7 +106,7 @@ def main():
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (the sharded path is design only); --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
