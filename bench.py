@@ -67,11 +67,11 @@ def flops_per_pair(spec) -> float:
         dot products, gaps and the phase constants (20) + 3 (1 + PG)
         sin/cos; with one wave per direction (16 panels, PG = 2) the second
         panel's phase is a product instead: 3 (2 x 30 + 12) + 20       = 236
-    scale factors and series coefficients, once per triangle (shared by
-        its 8 lanes)                                                    = 62
+    scale factors and series coefficients (through r^7), once per
+        triangle (shared by its 8 lanes)                                = 54
     running-sum merges: 2 * 2 PG adds per lane every 32 triangles.
     A lane owns 2 PG nodes and consumes 8 triangles per batch, so per pair:
-        34 + (producer + 62 / 8) / (16 PG) + 1 / 16.
+        34 + (producer + 54 / 8) / (16 PG) + 1 / 16.
     The mixed form runs the same steps (FP32 sin/cos polynomials are shorter,
     but the count here is the FP64 one, used for both).
     """
@@ -79,7 +79,7 @@ def flops_per_pair(spec) -> float:
     PG = 2 if P % 16 == 0 else 1
     one_wave = P == 8 * PG
     producer = 3 * (2 * 30.0 + 12.0) + 20.0 if (one_wave and PG == 2) else 3 * (1 + PG) * 30.0 + 20.0
-    return 34.0 + (producer + 62.0 / 8) / (16 * PG) + 1.0 / 16
+    return 34.0 + (producer + 54.0 / 8) / (16 * PG) + 1.0 / 16
 
 
 def _progress(msg: str) -> None:

@@ -42,7 +42,10 @@ constexpr double kGapFloor32 = 1e-18;
 // Per-(triangle, direction) constants in LDS.  ce/co are the coefficients of
 // the divided-difference power series as a polynomial in the radius r:
 // Re = sum_m ce[m] r^(2m), Im = r sum_m co[m] r^(2m) (see series_coefs).
-constexpr int kNC64 = 5;                        // series through r^9 (FP64 form)
+// FP64 form: series through r^7; the first omitted term is below
+// 9 G^8 / 10! of the leading 1/2, 1e-16 at the largest threshold the form
+// accepts (G < 0.05) and 2.5e-22 at the default 0.01
+constexpr int kNC64 = 4;
 constexpr int kNC32 = (kMixedSeriesN + 1) / 2;  // through r^kMixedSeriesN (mixed form)
 struct Scal64 { double Ka, Kb, rthr, pad; double ce[kNC64], co[kNC64]; };   // ce, co carry the factor J
 struct Scal32 { double J; float rthr, Ka, Kb, pad; float ce[kNC32], co[kNC32]; }; // Ka, Kb, ce, co without J
@@ -452,7 +455,7 @@ __device__ __forceinline__ void direct_wave_body(
     }
 }
 
-// FP64 form: its LDS batch (10 KB per wave, 40 KB per block) allows 4
+// FP64 form: its LDS batch (9.75 KB per wave, 39.5 KB per block) allows 4
 // blocks per CU.  ONE: one wave per direction (the wave starts at panel 0).
 template <int PG, bool ONE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_direct_wave(
