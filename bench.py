@@ -48,7 +48,7 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (256 CU x 2.4 GHz x 128 FLOP/cl
 # read off a 1 GiB device copy in the same runs
 # (profiles/k_direct_wave_fp64_level7_large_rule.md).  Re-measure after any
 # change to the kernel; other workloads were not measured.
-MEASURED_TRAFFIC = {"level7-large-rule": (3268320.3125 * 2.0 + 312408.25) * 1024.0}
+MEASURED_TRAFFIC = {"level7-large-rule": (3260738.6875 * 2.0 + 151552.0) * 1024.0}
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (256 CU x 2.4 GHz x 256 FLOP/clk)
 
 
