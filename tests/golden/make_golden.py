@@ -81,6 +81,25 @@ def adjoint_case(name, level=4, spec=RULE_SMALL, amp=0.05, s=1.0):
     print(f"{name}: d2={d2!r} |grad|max={np.abs(g).max():.3e} ({dt:.1f}s)", flush=True)
 
 
+def nufft_sampled(name, level, tri_rule, rule, n_samples=512, seed=13):
+    """The direct point sum of a level-``level`` icosphere's point cloud
+    (``tri_rule``: the 7-point or the 8x8 Gauss-Legendre triangle rule) at
+    ``n_samples`` seeded nodes of ``rule`` (the full-size NUFFT parity case);
+    sum |c| is stored for the tolerance tol * sum |c|."""
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(len(rule), size=n_samples, replace=False))
+    v, f = icosphere(level)
+    pts, c = oracle.point_cloud(v, f, tri_rule)
+    t = time.time()
+    mu = oracle.point_sum(pts, c, rule.nodes[idx])
+    dt = time.time() - t
+    np.savez(os.path.join(HERE, name + ".npz"), idx=idx, nodes=rule.nodes[idx], mu_re=mu.real,
+             mu_im=mu.imag, level=level, tri_rule=tri_rule, sum_abs_c=np.sum(np.abs(c)),
+             n_points=len(c), note="oracle.point_sum of oracle.point_cloud at sampled rule nodes; "
+                                   "written by make_golden.py")
+    print(f"{name}: {n_samples} nodes x {len(c)} points in {dt:.1f}s", flush=True)
+
+
 JOBS = {
     "adjoint_level4_small_rule": lambda: adjoint_case("adjoint_level4_small_rule"),
     "small_rule_levels": lambda: d2_levels("small_rule_levels", range(0, 6), RULE_SMALL),
@@ -88,7 +107,15 @@ JOBS = {
     "level7_large_rule_sampled": lambda: sampled("level7_large_rule_sampled", 7, RULE_LARGE),
     "large_rule_level3": lambda: d2_levels("large_rule_levels", [3], RULE_LARGE),
     "large_rule_level4": lambda: d2_levels("large_rule_levels", [3, 4], RULE_LARGE),
-    "small_rule_level7": lambda: d2_levels("small_rule_levels", [7], RULE_SMALL),
+    "large_rule_level5": lambda: d2_levels("large_rule_levels", [3, 4, 5], RULE_LARGE),
+    # level 7, 7-point rule (2,293,760 points) on the 8,388,608-node ball rule
+    "nufft_level7_large_rule_sampled": lambda: nufft_sampled(
+        "nufft_level7_large_rule_sampled", 7, "dunavant7", _rule(RULE_LARGE)),
+    # the paper's configuration: level 7, 8x8 GL rule (20,971,520 points) on
+    # the M = 128 lattice of [-xi_max, xi_max]^3 with xi_max = 2 pi 5
+    "nufft_level7_paper_lattice_sampled": lambda: nufft_sampled(
+        "nufft_level7_paper_lattice_sampled", 7, "gl8x8", oracle.cube_trapezoid_rule(2.0 * np.pi * 5.0, 128)),
+    "small_rule_level7": lambda: d2_levels("small_rule_levels", [6, 7], RULE_SMALL),
 }
 
 if __name__ == "__main__":

@@ -4,6 +4,7 @@ transform against the oracle's direct sum over exactly the same point cloud
 triangle transform (reported, unpinned)."""
 import ctypes as C
 import math
+import os
 
 import numpy as np
 import pytest
@@ -260,5 +261,44 @@ def test_nufft_dense_points_split_spread(hsd_ctx, orc):
     err = np.max(np.abs(got[idx] - ref)) / np.sum(np.abs(c))
     print(f"dense lattice spread: {len(c)} points, max |err| / sum|c| = {err:.2e}")
     assert err <= 1e-10
+    mesh.close()
+    rule.close()
+
+
+@pytest.mark.parametrize("name,tol", [("nufft_level7_large_rule_sampled", 1e-9),
+                                      ("nufft_level7_paper_lattice_sampled", 1e-7),
+                                      ("nufft_level7_paper_lattice_sampled", 1e-10)])
+def test_nufft_full_size_against_stored_point_sum(hsd_ctx, name, tol):
+    """The NUFFT at the sizes the benchmark runs, against the oracle's direct
+    point sum stored at 512 seeded nodes (eqs. change_variable_approx,
+    def_nufft_type1, source_scale; sections 3.1 and 3.3):
+      * level-7 icosphere, 7-point rule (2,293,760 points), 8,388,608-node
+        ball rule (r <= 256): type 3 with fine grid n2 = 729 (three radix-9
+        stages), kernel width 10 at tol 1e-9;
+      * level-7 icosphere, 8x8 Gauss-Legendre rule (20,971,520 points), the
+        paper's M = 128 lattice on [-xi_max, xi_max]^3, xi_max = 2 pi 5:
+        type 1 on the lattice, at the benchmark's tol 1e-7 and at 1e-10.
+    Bar: |error| <= tol * sum |c| at every sampled node."""
+    from conftest import golden_path
+    path = golden_path(name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip("fixture not generated")
+    z = np.load(path)
+    v, f = icosphere(int(z["level"]))
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    if "lattice" in name:
+        rule = hsd.Rule.cube_trapezoid(hsd_ctx, 2.0 * math.pi * 5.0, 128)
+        p = hsd.Params(s=10.0, freq_unit=2 * math.pi, method="nufft3", tri_rule=str(z["tri_rule"]),
+                       nufft_tol=tol)
+    else:
+        rule = hsd.Rule.spherical_product(hsd_ctx, 256.0, 16, 16, 128, 256)
+        p = hsd.Params(method="nufft3", tri_rule=str(z["tri_rule"]), nufft_tol=tol)
+    idx = z["idx"]
+    assert np.array_equal(rule.nodes()[0][idx], z["nodes"])
+    got = hsd.transform_rule(hsd_ctx, mesh, rule, p)[idx]
+    ref = z["mu_re"] + 1j * z["mu_im"]
+    err = np.max(np.abs(got - ref)) / float(z["sum_abs_c"])
+    print(f"{name} ({int(z['n_points'])} points) tol {tol:.0e}: max |err| / sum|c| = {err:.2e}")
+    assert err <= tol
     mesh.close()
     rule.close()
