@@ -37,18 +37,24 @@ def _area(v, f):
 def _mu_tol(v, f, nodes, k=20.0, tau=1e-2, h=None):
     """Per-node bound for two FP64 evaluations of mu_h^: phase rounding
     (eps |xi|) plus the closed branch's eps/G error with G >= tau, times the
-    total J = 2 area.  h: half panel width of a spherical-product rule with
-    16 nodes per panel (the wave-per-direction kernel), whose nodes below
-    the first panel centre form their small half-gap phases as products of
-    larger angles: absolute rounding, divided by r G >= tau in the closed
-    branch, bounded by 160 eps / tau per unit area."""
+    total J = 2 area.
+
+    h: half panel width of a spherical-product rule with 16 nodes per panel
+    (the wave-per-direction kernel).  That kernel forms the phase of node
+    r = m -+ h x (panel centre m) as the product of exp(-i m c) and
+    exp(-+i h x c), so a half-gap sine carries an absolute rounding
+    proportional to the larger angle (m + h |x|) c instead of r c: the
+    closed branch's eps/(r G) term grows by rho = (m + h |x|) / r (1 for the
+    nodes above their panel centre, up to 188 for the smallest node of the
+    first panel)."""
     eps = 1.1e-16
     A = max(_area(v, f), 1e-300)
     r = np.linalg.norm(nodes, axis=1)
-    tol = k * eps * (1.0 + r) * A + 8.0 * eps / tau * A
+    rho = 1.0
     if h is not None:
-        tol = tol + np.where(r < h, 160.0 * eps / tau * A, 0.0)
-    return tol
+        m = (2.0 * np.floor(r / (2.0 * h)) + 1.0) * h
+        rho = (m + np.abs(r - m)) / np.maximum(r, 1e-300)
+    return k * eps * (1.0 + r) * A + 8.0 * eps * rho / tau * A
 
 
 def test_rule_nodes_match_oracle_rule(hsd_ctx, orc):

@@ -294,11 +294,16 @@ def test_nufft_full_size_against_stored_point_sum(hsd_ctx, name, tol):
         rule = hsd.Rule.spherical_product(hsd_ctx, 256.0, 16, 16, 128, 256)
         p = hsd.Params(method="nufft3", tri_rule=str(z["tri_rule"]), nufft_tol=tol)
     idx = z["idx"]
-    assert np.array_equal(rule.nodes()[0][idx], z["nodes"])
+    # the library's rule (its own Gauss-Legendre) and the oracle's agree to
+    # rounding; a node offset d moves each point's phase by at most
+    # |x| |d| <= |d| (the points lie in the unit ball), which the bar adds
+    dnode = np.max(np.linalg.norm(rule.nodes()[0][idx] - z["nodes"], axis=1))
+    assert dnode <= 1e-13 * np.max(np.abs(z["nodes"]))
     got = hsd.transform_rule(hsd_ctx, mesh, rule, p)[idx]
     ref = z["mu_re"] + 1j * z["mu_im"]
     err = np.max(np.abs(got - ref)) / float(z["sum_abs_c"])
-    print(f"{name} ({int(z['n_points'])} points) tol {tol:.0e}: max |err| / sum|c| = {err:.2e}")
-    assert err <= tol
+    print(f"{name} ({int(z['n_points'])} points) tol {tol:.0e}: max |err| / sum|c| = {err:.2e} "
+          f"(node offset {dnode:.1e})")
+    assert err <= tol + dnode
     mesh.close()
     rule.close()

@@ -78,21 +78,20 @@ def mu_tol(v, f, nodes, k=20.0, tau=1e-2, h=None):
     G >= tau, each times the triangle's J = 2 area.
 
     h: half panel width of a spherical-product rule evaluated by the
-    wave-per-direction kernel.  Its nodes below the first panel centre
-    (r = h - h x_k < h) take their half-gap phases as products of the
-    centre phase and the node offset's phase, whose angles exceed the
-    node's own: the small half-gap sine then carries an absolute (not a
-    relative) rounding of a few ulp, which the closed branch divides by
-    r G >= tau, in Re and Im and for both gaps.  Bound for those nodes:
-    160 eps / tau per unit area (the worst case measured over levels 0-3
-    and three rules is 72)."""
+    wave-per-direction kernel.  It forms the phase of node r = m -+ h x
+    (panel centre m) as the product of exp(-i m c) and exp(-+i h x c): a
+    half-gap sine then carries an absolute rounding proportional to the
+    larger angle (m + h |x|) c rather than r c, so the closed branch's
+    eps/(r G) term grows by rho = (m + h |x|) / r (1 above the panel centre,
+    up to 188 at the smallest node of the first panel)."""
     eps = 1.1e-16
     A = _area(v, f)
     r = np.linalg.norm(nodes, axis=1)
-    tol = k * eps * (1.0 + r) * A + 8.0 * eps / tau * A
+    rho = 1.0
     if h is not None:
-        tol = tol + np.where(r < h, 160.0 * eps / tau * A, 0.0)
-    return tol
+        m = (2.0 * np.floor(r / (2.0 * h)) + 1.0) * h
+        rho = (m + np.abs(r - m)) / np.maximum(r, 1e-300)
+    return k * eps * (1.0 + r) * A + 8.0 * eps * rho / tau * A
 
 
 def test_sincos64_against_libm():
@@ -252,7 +251,8 @@ def test_wave_kernel_small_radius_nodes(orc, level, spec):
     """FP64 wave-kernel bodies on coarse meshes (edges up to 1.05), where the
     nodes below the first panel centre take the closed branch near its
     threshold r G = tau: every node within the per-node bound, and the
-    nodes at r >= h within the bound without the small-radius term."""
+    nodes at r >= h (rho <= 2 there) within the bound for directly
+    evaluated phases (rho = 1)."""
     rng = np.random.default_rng(level)
     v, f = icosphere(level)
     v = rotate(perturb_radial(v, 0.05, rng), random_rotation(rng))
