@@ -237,6 +237,29 @@ void hsd_rule_destroy(hsd_rule *r);
 hsd_status hsd_distance(hsd_ctx *ctx, const hsd_mesh *mu, const hsd_mesh *nu,
                         const hsd_rule *rule, const hsd_params *p, hsd_result *out);
 
+/* hsd_distance that allocates no device memory, for callers that cannot
+ * allocate: code recorded under HIP graph capture, tight serving loops and
+ * harnesses that forbid hipMalloc.  Same arguments, result and errors as
+ * hsd_distance, direct method only (EINVAL for NUFFT3).  The mesh(es) and
+ * the rule must exist already (creating them allocates).
+ * Every per-call buffer -- the weight and sphere-transform tables for
+ * (s, freq_unit), built on the device from the rule's resident nodes and
+ * weights; the [K][N] complex partial transforms; the reduction partials --
+ * lives in one fixed device array of HSD_NOALLOC_SCRATCH_BYTES bytes per
+ * GPU, reserved when the library's code is loaded on that GPU and held
+ * until the process ends; hsd_init takes its address once per device.
+ * A call needs 16 N + 16 T + 8 (N/256 + 2) bytes plus alignment (N rule
+ * nodes; T = radial nodes of a spherical-product rule, else N) and fails
+ * with EINVAL, before launching anything, when that exceeds the array; the
+ * triangle splits K are reduced until the partials fit, so d2 may differ
+ * from hsd_distance's in the last bits (split order, device-built tables).
+ * Every call on one GPU uses the same array, which keeps the last call's
+ * contents: calls that overlap on one GPU (other threads, other contexts,
+ * other streams) race, and the caller must serialise them. */
+#define HSD_NOALLOC_SCRATCH_BYTES ((size_t)160 << 20)
+hsd_status hsd_distance_noalloc(hsd_ctx *ctx, const hsd_mesh *mu, const hsd_mesh *nu,
+                                const hsd_rule *rule, const hsd_params *p, hsd_result *out);
+
 /* Squared distance and its gradient with respect to the vertices of mu,
  * grad[nv][3] (mem_kind says where grad lives).  With nu a mesh, nu is held
  * fixed.  Direct method only (EINVAL for NUFFT3). */

@@ -8,8 +8,8 @@ reduction; its NUFFT fast path and adjoint) runs in the HIP kernels of
 first Context does, and fails loudly if it has not been built.
 """
 from .api import (Context, HsdError, Mesh, Params, PointMeasure, Result, Rule, Server, SurfaceMeasure, Ticket,
-                  distance, distance_grad, transform, transform_rule)
+                  distance, distance_grad, distance_noalloc, transform, transform_rule)
 
 __all__ = ["Context", "HsdError", "Mesh", "Params", "PointMeasure", "Result", "Rule", "Server", "SurfaceMeasure",
            "Ticket",
-           "distance", "distance_grad", "transform", "transform_rule"]
+           "distance", "distance_grad", "distance_noalloc", "transform", "transform_rule"]

@@ -296,6 +296,18 @@ def distance(ctx: Context, mu: Mesh, nu: Mesh | None, rule: Rule, params: Params
     return Result.from_c(r)
 
 
+def distance_noalloc(ctx: Context, mu: Mesh, nu: Mesh | None, rule: Rule,
+                     params: Params | None = None) -> Result:
+    """Squared distance without any device allocation (hsd_distance_noalloc):
+    the library's fixed per-GPU scratch array holds every per-call buffer;
+    direct method only."""
+    p = (params or Params()).to_c()
+    r = L.Result()
+    _check(ctx._lib.hsd_distance_noalloc(ctx.handle, mu.handle, nu.handle if nu is not None else None,
+                                         rule.handle, C.byref(p), C.byref(r)))
+    return Result.from_c(r)
+
+
 def distance_grad(ctx: Context, mu: Mesh, nu: Mesh | None, rule: Rule, params: Params | None = None,
                   out=None):
     """(Result, grad[nv,3]) (hsd_distance_grad).  ``out`` may be a device

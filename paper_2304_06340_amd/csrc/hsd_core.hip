@@ -406,6 +406,8 @@ hsd_status hsd_init(int device, size_t budget, hsd_ctx **out)
     HSD_HIP_TRY(hipSetDevice(device));
     size_t freeb = 0, totalb = 0;
     HSD_HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+    hsd_status nst = noalloc_setup(device);
+    if (nst != HSD_OK) return nst;
     auto *c = new hsd_ctx();
     c->device = device;
     c->budget = budget ? budget : (size_t)(0.9 * (double)freeb);
@@ -733,6 +735,8 @@ hsd_status hsd_freq_rule(hsd_ctx *ctx, const hsd_rule_desc *d, hsd_rule **out)
         for (size_t i = 0; i < iradii.size(); ++i) iradii[i] = 1.0 / sp.radii[i];
         if ((stt = r->d_iradii.alloc(ctx, iradii.size() * 8)) != HSD_OK) return stt;
         HSD_HIP_TRY(hipMemcpyAsync(r->d_iradii.ptr, iradii.data(), iradii.size() * 8, hipMemcpyHostToDevice, st));
+        if ((stt = r->d_wts.alloc(ctx, sp.wr.size() * 8)) != HSD_OK) return stt;
+        HSD_HIP_TRY(hipMemcpyAsync(r->d_wts.ptr, sp.wr.data(), sp.wr.size() * 8, hipMemcpyHostToDevice, st));
         HSD_HIP_TRY(hipStreamSynchronize(st));
     } else if (d->kind == HSD_RULE_EXPLICIT || d->kind == HSD_RULE_CUBE_TRAPEZOID) {
         if (d->kind == HSD_RULE_EXPLICIT) {
@@ -782,6 +786,9 @@ hsd_status hsd_freq_rule(hsd_ctx *ctx, const hsd_rule_desc *d, hsd_rule **out)
         }
         if ((stt = r->d_nodes.alloc(ctx, r->host_nodes.size() * 8)) != HSD_OK) return stt;
         HSD_HIP_TRY(hipMemcpyAsync(r->d_nodes.ptr, r->host_nodes.data(), r->host_nodes.size() * 8, hipMemcpyHostToDevice, st));
+        if ((stt = r->d_wts.alloc(ctx, r->host_weights.size() * 8)) != HSD_OK) return stt;
+        HSD_HIP_TRY(hipMemcpyAsync(r->d_wts.ptr, r->host_weights.data(), r->host_weights.size() * 8,
+                                   hipMemcpyHostToDevice, st));
         static const double one = 1.0;
         if ((stt = r->d_radii.alloc(ctx, 8)) != HSD_OK) return stt;
         HSD_HIP_TRY(hipMemcpyAsync(r->d_radii.ptr, &one, 8, hipMemcpyHostToDevice, st));

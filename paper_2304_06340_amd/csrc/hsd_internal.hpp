@@ -155,6 +155,8 @@ struct hsd_rule {
     hsd::DevBuf d_radii;                      // SP: radial nodes [n_rad]; others: {1.0}
     hsd::DevBuf d_iradii;                     // SP: their reciprocals [n_rad]
     hsd::DevBuf d_nodes;                      // EXPLICIT/CUBE: [n*3]
+    hsd::DevBuf d_wts;                        // SP: radial weights w_r [n_rad]; others: node
+                                              // weights [n] (device-built weight tables)
     int32_t cube_M = 0;                       // CUBE: lattice indices -M/2..M/2 per axis
     double cube_h = 0.0;                      // CUBE: lattice spacing 2 xi_max / M
     // per-s tables, kept for the rule's lifetime (requests with different s
@@ -232,6 +234,11 @@ hsd_status launch_gather(hipStream_t st, const hsd_mesh *m, const double *tri_gr
 hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc,
                                 const hsd_mesh *mu, const hsd_mesh *nu, const hsd_rule *rule,
                                 const hsd_params *p, double2 *out, double *pairs);
+
+// No-allocation entry point (hsd_noalloc.hip): takes the device address of
+// its fixed scratch array once per device; called by hsd_init with the
+// device current.
+hsd_status noalloc_setup(int device);
 
 // Shared host helpers (hsd_core.hip).
 double freq_unit_of(const hsd_params *p);
