@@ -42,44 +42,68 @@ WORKLOADS = {
 }
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector (256 CU x 2.4 GHz x 128 FLOP/clk)
-
-# HBM bytes per launch of k_direct_wave<2, true> (FP64) measured with rocprofv3 for the
-# current kernel revision: FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the factors
-# read off a 1 GiB device copy in the same runs
-# (profiles/k_direct_wave_fp64_level7_large_rule.md).  Re-measure after any
-# change to the kernel; other workloads were not measured.
-MEASURED_TRAFFIC = {"level7-large-rule": (3260738.6875 * 2.0 + 151552.0) * 1024.0}
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector (256 CU x 2.4 GHz x 256 FLOP/clk)
 
+# Sources whose compiled code is the FP64 direct-sum kernel; their hash stamps
+# the HBM traffic measured for it below.
+KERNEL_SOURCES = ("paper_2304_06340_amd/csrc/hsd_direct_wave.hip", "paper_2304_06340_amd/csrc/hsd_math.hpp",
+                  "paper_2304_06340_amd/csrc/hsd_internal.hpp")
 
-def flops_per_pair(spec) -> float:
+# HBM bytes per launch of k_direct_wave<2, true> (FP64) from rocprofv3:
+# FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, the factors read off a 1 GiB device
+# copy in the same runs (profiles/k_direct_wave_fp64_level7_large_rule.md),
+# with the hash of KERNEL_SOURCES when they were taken.  A kernel whose
+# sources hash differently reports traffic null: the counters no longer
+# describe it.
+MEASURED_TRAFFIC = {"level7-large-rule": (None, "")}
+
+
+def kernel_revision() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def flops_per_pair(spec, form="fp64") -> float:
     """Algorithmic FLOPs (FMA = 2) per triangle-node pair of the
     wave-per-direction direct-sum kernel (16-node panels), counted from its
-    source along the closed branch (the series branch replaces it for the few
-    pairs with a small phase spread); the count agrees with the FP64
-    operations of the compiled blocks.
+    source along the closed branch (the series branch replaces it for the
+    pairs with a small phase spread).
 
-    consumer, per node: 3 phase products (6 each) + closed-branch numerators
-        (2 + 6) + complex multiply-accumulate (8)                      = 34
-    one sin/cos with its argument (turn-table reduction, degree-9/8
-        polynomials, rotation)                                          = 30
+    FP64 form, consumer per node: 3 phase products (6 each) + the closed
+    branch's two numerators from the sqrt(K)-scaled half-gap phases (2 MUL +
+    2 FMA = 6) + complex multiply-accumulate (8)                          = 32
+    one FP64 sin/cos with its argument (turn-table reduction, degree-9/8
+        polynomials, rotation)                                             = 30
     producer, per (triangle, lane), once per batch of 8 triangles:
-        dot products, gaps and the phase constants (20) + 3 (1 + PG)
-        sin/cos; with one wave per direction (16 panels, PG = 2) the second
-        panel's phase is a product instead: 3 (2 x 30 + 12) + 20       = 236
-    scale factors and series coefficients (through r^7), once per
-        triangle (shared by its 8 lanes)                                = 54
+        dot products, gaps and the phase constants (20) + 3 (1 + PG) sin/cos;
+        with one wave per direction (16 panels, PG = 2) the second panel's
+        phase is a product instead: 3 (2 x 30 + 12) + 20                   = 236
+        sqrt(K_a), sqrt(K_b) (reciprocal, products, two square roots: 10)
+        and the scaling of the two half-gap centre rows (4 PG)             = 10 + 4 PG
+    series coefficients (through r^7) and threshold, once per triangle
+        (shared by its 8 lanes)                                            = 46
     running-sum merges: 2 * 2 PG adds per lane every 32 triangles.
     A lane owns 2 PG nodes and consumes 8 triangles per batch, so per pair:
-        34 + (producer + 54 / 8) / (16 PG) + 1 / 16.
-    The mixed form runs the same steps (FP32 sin/cos polynomials are shorter,
-    but the count here is the FP64 one, used for both).
+        32 + (producer + 46 / 8) / (16 PG) + 1 / 16.
+
+    Mixed form (FP32 node arithmetic): consumer 34 per node (the K factors
+    applied to the phase sines: 2 more MUL); producer 20 + 3 (1 + PG) FP32
+    sin/cos of 36 each (FP64 reduction 5, polynomials with two-float leading
+    coefficients 31); K_a, K_b, threshold and series coefficients through
+    r^11 once per triangle: 60; batch flush: 2 adds per slot and batch.
     """
     P = spec["n_panels"]
     PG = 2 if P % 16 == 0 else 1
+    if form == "mixed":
+        return 34.0 + (20.0 + 3 * (1 + PG) * 36.0 + 60.0 / 8) / (16 * PG) + 2.0 / 8
     one_wave = P == 8 * PG
     producer = 3 * (2 * 30.0 + 12.0) + 20.0 if (one_wave and PG == 2) else 3 * (1 + PG) * 30.0 + 20.0
-    return 34.0 + (producer + 54.0 / 8) / (16 * PG) + 1.0 / 16
+    producer += 10.0 + 4 * PG
+    return 32.0 + (producer + 46.0 / 8) / (16 * PG) + 1.0 / 16
 
 
 def _progress(msg: str) -> None:
@@ -166,29 +190,34 @@ def main():
     }
     flop_pair = flops_per_pair(spec)
     achieved = flop_pair * pairs / (kern_ms * 1e-3) / 1e12
+    rev = kernel_revision()
+    traffic, traffic_rev = MEASURED_TRAFFIC.get(args.workload, (None, ""))
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                        "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                       "traffic": MEASURED_TRAFFIC.get(args.workload),
+                       "traffic": traffic if traffic_rev == rev else None,
                        "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, "
-                                       "scaled by a plain copy's counters",
+                                       "scaled by a plain copy's counters, for kernel revision "
+                                       f"{traffic_rev or 'none'} (this build: {rev}; null when they differ)",
                        "kernel": "k_direct_wave (FP64)", "kernel_ms": kern_ms,
-                       "flops_per_pair": flop_pair}
+                       "kernel_revision": rev, "flops_per_pair": flop_pair}
     if not args.no_mixed:
         mixed = hsd.Params(s=1.0, form="mixed")
         wallm, resm = run(mixed, args.steps, args.warmup)
         _progress(f"mixed {wallm * 1e3:.1f} ms per distance")
         rel = abs(resm[-1].d2 - d2_64) / d2_64
         kern_m = float(np.mean([r.transform_ms for r in resm]))
-        ach_m = flop_pair * pairs / (kern_m * 1e-3) / 1e12
+        flop_m = flops_per_pair(spec, "mixed")
+        ach_m = flop_m * pairs / (kern_m * 1e-3) / 1e12
         out["mixed"] = {"pairs_per_s": pairs / wallm, "ms_per_step": wallm * 1e3,
                         "distances_per_s": 1.0 / wallm, "rel_err_vs_fp64": rel,
                         "rel_err_stated": resm[-1].rel_err_stated,
                         "speedup_vs_fp64": wall64 / wallm, "kernel_ms": kern_m,
                         "roofline": {"bound": "alu", "achieved": ach_m, "peak": FP32_PEAK_TFLOPS,
                                      "unit": "TFLOP/s", "frac": ach_m / FP32_PEAK_TFLOPS,
-                                     "kernel": "k_direct_wave_mixed",
-                                     "note": "FP32 peak; the kernel's FP64 phase reduction and "
-                                             "FP64 accumulation run at the FP64 rate"}}
+                                     "kernel": "k_direct_wave_mixed", "flops_per_pair": flop_m,
+                                     "note": "FP32 peak; the kernel's FP64 phase reduction, "
+                                             "series-branch accumulation and batch flushes run at "
+                                             "the FP64 rate"}}
     if not args.no_nufft:
         # type-3 NUFFT fast path (Dunavant-7 points, tol 1e-9) on the same mesh and rule
         pn = hsd.Params(s=1.0, method="nufft3", nufft_tol=1e-9)

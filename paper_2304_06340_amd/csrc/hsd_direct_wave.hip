@@ -47,8 +47,8 @@ constexpr double kGapFloor32 = 1e-18;
 // accepts (G < 0.05) and 2.5e-22 at the default 0.01
 constexpr int kNC64 = 4;
 constexpr int kNC32 = (kMixedSeriesN + 1) / 2;  // through r^kMixedSeriesN (mixed form)
-struct Scal64 { double Ka, Kb, rthr, pad; double ce[kNC64], co[kNC64]; };   // ce, co carry the factor J
-struct Scal32 { double J; float rthr, Ka, Kb, pad; float ce[kNC32], co[kNC32]; }; // Ka, Kb, ce, co without J
+struct Scal64 { double rthr, pad; double ce[kNC64], co[kNC64]; };   // ce, co carry the factor |J|
+struct Scal32 { float rthr, Ka, Kb, c0lo; float ce[kNC32], co[kNC32]; };   // Ka, Kb, ce, co carry |J|
 
 template <int PG> struct Batch64 {
     Scal64 sc[kTB];
@@ -147,6 +147,14 @@ HSD_HD cs64 group_first_phase(cs64 own, double hc, const cs64 *turn)
 // ONE: the wave covers all panels of its direction (w0 = 0); the second
 // panel's phase is then the first one's times e^{-2 i h c}, the square of the
 // group's panel-0 phase, instead of another sin/cos.
+//
+// The closed branch needs K_a sin^2(r a/2), K_a sin(r a/2) cos(r a/2) and
+// the same for b, with K_a = 2 |J| / (G a), K_b = 2 |J| / (G b).  The
+// centre phases of the two half gaps are stored times sqrt(K_a), sqrt(K_b),
+// so the consumer's phase products give sqrt(K) e^{-i r g/2} and the four
+// terms are two squares and two products of their parts.  The sign of J
+// (-1 for a second mesh) rides on the theta_mid phase row, the series
+// coefficients carry |J|.
 template <int PG, bool ONE>
 HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
                       const cs64 *turn, Scal64 *sc, cs64 Bk[3], cs64 Cp[PG][3])
@@ -168,16 +176,23 @@ HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, i
                 Cp[q][c] = sincos64_tab((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c], turn);
         }
     }
+    // 1/ac and 1/bc from one reciprocal of ac bc (both gaps are floored at
+    // 1e-150, so the product stays a normal number)
+    const double aJ = fabs(td.J);
+    const double rab = rcp64(td.ac * td.bc);
+    const double t = 2.0 * aJ * td.iG;
+    const double ska = __builtin_sqrt(t * (td.bc * rab)), skb = __builtin_sqrt(t * (td.ac * rab));
+    const double sgn = td.J < 0.0 ? -1.0 : 1.0;
+#pragma unroll
+    for (int q = 0; q < PG; ++q) {
+        Cp[q][0] = cs64{sgn * Cp[q][0].c, sgn * Cp[q][0].s};
+        Cp[q][1] = cs64{ska * Cp[q][1].c, ska * Cp[q][1].s};
+        Cp[q][2] = cs64{skb * Cp[q][2].c, skb * Cp[q][2].s};
+    }
     if (sc) {
-        // 1/ac and 1/bc from one reciprocal of ac bc (both gaps are floored
-        // at 1e-150, so the product stays a normal number)
-        const double rab = rcp64(td.ac * td.bc);
-        const double t = 2.0 * td.J * td.iG;
-        sc->Ka = t * (td.bc * rab);
-        sc->Kb = t * (td.ac * rab);
         sc->rthr = tau * td.iG;
         sc->pad = 0.0;
-        series_coefs<kNC64>(td.ac, td.bc, td.J, sc->ce, sc->co);
+        series_coefs<kNC64>(td.ac, td.bc, aJ, sc->ce, sc->co);
     }
 }
 
@@ -200,13 +215,12 @@ HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 (*Cp)[3], d
         for (int sg = 0; sg < 2; ++sg) {
             const int slot = 2 * pl + sg;
             const double r = sg == 0 ? m + hx : m - hx;
+            // E[1], E[2] carry sqrt(K_a), sqrt(K_b) (see produce64)
             cs64 E[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) E[c] = sg == 0 ? pmul(Cp[pl][c], Bk[c]) : pmulc(Cp[pl][c], Bk[c]);
-            const double Pv = sc.Kb * E[2].s;
-            const double Pu = sc.Ka * E[1].s;
-            double Yr = __builtin_fma(Pv, E[2].s, Pu * E[1].s);
-            double Xr = __builtin_fma(Pv, E[2].c, -Pu * E[1].c);
+            double Yr = __builtin_fma(E[2].s, E[2].s, E[1].s * E[1].s);
+            double Xr = __builtin_fma(E[2].s, E[2].c, -(E[1].s * E[1].c));
             if (r < sc.rthr) {
                 const double r2 = r * r;
                 double pe, po;
@@ -222,42 +236,57 @@ HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 (*Cp)[3], d
 
 // Producer, mixed: FP32 phases from FP64-reduced angles.  Cp is the
 // triangle's whole row, indexed by panel offset in the wave; part j fills
-// panels j + kNH q.
+// panels j + kNH q.  The sign of J (-1 for a second mesh) rides on the
+// theta_mid phase row; the closed-branch factors K_a = 2 |J| / (G a),
+// K_b = 2 |J| / (G b) and the series coefficients carry |J|, each rounded
+// once to FP32 (a relative error that differs between directions, since the
+// gaps do).  The series' constant term |J|/2 does not depend on the
+// direction, so its FP32 rounding would be the same for every triangle of
+// equal area (a symmetric mesh has few distinct areas) and would not
+// average out: it is kept as the two-float pair ce[0] + c0lo.
 template <int PG>
 HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
                       Scal32 *sc, cs32 Bk[3], cs32 (*Cp)[3])
 {
     const double fr[3] = {td.tmid, 0.5 * td.ac, 0.5 * td.bc};
     const double hx = hx_tab[j];
+    const float sgn = td.J < 0.0 ? -1.0f : 1.0f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         Bk[c] = sincos32_acc(hx * fr[c]);
 #pragma unroll
-        for (int q = 0; q < PG; ++q)
-            Cp[j + kNH * q][c] = sincos32_acc((double)(2 * (w0 + j + kNH * q) + 1) * h * fr[c]);
+        for (int q = 0; q < PG; ++q) {
+            cs32 e = sincos32_acc((double)(2 * (w0 + j + kNH * q) + 1) * h * fr[c]);
+            if (c == 0) e = cs32{sgn * e.c, sgn * e.s};
+            Cp[j + kNH * q][c] = e;
+        }
     }
     if (sc) {
+        const double aJ = fabs(td.J);
         const double rab = rcp64(td.ac * td.bc);   // gaps floored at 1e-18
-        sc->Ka = (float)(2.0 * td.iG * (td.bc * rab));
-        sc->Kb = (float)(2.0 * td.iG * (td.ac * rab));
+        const double t = 2.0 * aJ * td.iG;
+        sc->Ka = (float)(t * (td.bc * rab));
+        sc->Kb = (float)(t * (td.ac * rab));
         sc->rthr = (float)(fmax(tau, kMixedTau) * td.iG);   // decides the branch only
-        sc->pad = 0.0f;
-        sc->J = td.J;
         double ce[kNC32], co[kNC32];
-        series_coefs<kNC32>(td.ac, td.bc, 1.0, ce, co);
+        series_coefs<kNC32>(td.ac, td.bc, aJ, ce, co);
+        sc->ce[0] = (float)ce[0];
+        sc->c0lo = (float)(ce[0] - (double)sc->ce[0]);
 #pragma unroll
-        for (int m = 0; m < kNC32; ++m) {
-            sc->ce[m] = (float)ce[m];
-            sc->co[m] = (float)co[m];
-        }
+        for (int m = 1; m < kNC32; ++m) sc->ce[m] = (float)ce[m];
+#pragma unroll
+        for (int m = 0; m < kNC32; ++m) sc->co[m] = (float)co[m];
     }
 }
 
-// Consumer, mixed: FP32 node arithmetic on J-free quantities; the factor J
-// (closed branch) or r^2 J (series) is applied in FP64 as each contribution
-// is added to its FP64 running sum.  Rounding J or r^2 to FP32 would give
-// every triangle of equal area (most of a symmetric mesh) the same relative
-// error, which does not average out.
+// Consumer, mixed: FP32 node arithmetic.  The closed branch's terms come out
+// scaled by J and r^2 and are summed in FP32 over one batch of 8 triangles
+// (acc), which the caller flushes into the FP64 running totals (tot).  The
+// series branch's J-scaled terms are added to tot directly, times r^2 in
+// FP64: at small r G all triangles' terms are close to J/2 with nearly the
+// same phase, so an FP32 partial sum over a batch would grow linearly and
+// its rounding would outweigh the terms' own; and r^2 rounded to FP32 would
+// give every contribution of a node the same relative error.
 //
 // Lane layout (mixed form): lane = (po, sg, k) = (lane / 16, lane / 8 % 2,
 // lane % 8) holds node m_p + h x_k (sg = 0) or m_p - h x_k (sg = 1) of the
@@ -273,8 +302,8 @@ HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, i
 // every other node's closed branch carries.
 template <int PG>
 HSD_HD void consume32(const Scal32 &scr, const cs32 Bk[3], const cs32 (*Cp)[3],
-                      const float *rf, const float *r2f, const double *r2d,
-                      bool conj, double *acc_re, double *acc_im)
+                      const float *rf, const float *r2f, const double *r2d, bool conj, float *acc_re,
+                      float *acc_im, double *tot_re, double *tot_im)
 {
     constexpr int NS = 2 * PG;
     const Scal32 sc = scr;   // one read of the triangle's constants per triangle
@@ -284,14 +313,12 @@ HSD_HD void consume32(const Scal32 &scr, const cs32 Bk[3], const cs32 (*Cp)[3],
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         const cs32 E0 = pmul(Cp[4 * q][0], B[0]);
-        float tre, tim;
-        double scale;
         if (rf[q] < sc.rthr) {
-            // Re of the series minus its constant 1/2; the 1/2 term is added
-            // last, in one fused step with the rest of the product already
-            // summed, so that the rounding sees the exact total (1/2 rounded
-            // first and a sub-ulp rest added after it would err the same way
-            // for every triangle of a node).
+            // Re of the series minus its constant term; the constant term
+            // (J/2) is added last, in one fused step with the rest of the
+            // product already summed, so that the rounding sees the exact
+            // total (J/2 rounded first and a sub-ulp rest added after it
+            // would err the same way for every triangle of a node)
             const float r2 = r2f[q];
             float pe = sc.ce[kNC32 - 1], po = sc.co[kNC32 - 1];
 #pragma unroll
@@ -300,28 +327,26 @@ HSD_HD void consume32(const Scal32 &scr, const cs32 Bk[3], const cs32 (*Cp)[3],
             for (int m = kNC32 - 2; m >= 0; --m) po = __builtin_fmaf(po, r2, sc.co[m]);
             const float Yr = pe * r2;
             const float Xr = rf[q] * po;
-            tre = __builtin_fmaf(0.5f, E0.c, __builtin_fmaf(E0.c, Yr, E0.s * Xr));
-            tim = __builtin_fmaf(-0.5f, E0.s, __builtin_fmaf(E0.c, Xr, -E0.s * Yr));
-            scale = r2d[q] * sc.J;
+            const float yr = Yr + sc.c0lo;
+            const float tre = __builtin_fmaf(sc.ce[0], E0.c, __builtin_fmaf(E0.c, yr, E0.s * Xr));
+            const float tim = __builtin_fmaf(-sc.ce[0], E0.s, __builtin_fmaf(E0.c, Xr, -E0.s * yr));
+            tot_re[q] = __builtin_fma(r2d[q], (double)tre, tot_re[q]);
+            tot_im[q] = __builtin_fma(r2d[q], (double)tim, tot_im[q]);
         } else {
-            cs32 E[3];
-#pragma unroll
-            for (int c = 1; c < 3; ++c) E[c] = pmul(Cp[4 * q][c], B[c]);
-            const float Pv = sc.Kb * E[2].s;
-            const float Pu = sc.Ka * E[1].s;
-            const float Yr = __builtin_fmaf(Pv, E[2].s, Pu * E[1].s);
-            const float Xr = __builtin_fmaf(Pv, E[2].c, -Pu * E[1].c);
-            tre = __builtin_fmaf(E0.c, Yr, E0.s * Xr);
-            tim = __builtin_fmaf(E0.c, Xr, -E0.s * Yr);
-            scale = sc.J;
+            const cs32 E1 = pmul(Cp[4 * q][1], B[1]);
+            const cs32 E2 = pmul(Cp[4 * q][2], B[2]);
+            const float Pv = sc.Kb * E2.s;
+            const float Pu = sc.Ka * E1.s;
+            const float Yr = __builtin_fmaf(Pv, E2.s, Pu * E1.s);
+            const float Xr = __builtin_fmaf(Pv, E2.c, -Pu * E1.c);
+            acc_re[q] = __builtin_fmaf(E0.c, Yr, __builtin_fmaf(E0.s, Xr, acc_re[q]));
+            acc_im[q] = __builtin_fmaf(E0.c, Xr, __builtin_fmaf(-E0.s, Yr, acc_im[q]));
         }
-        acc_re[q] = __builtin_fma(scale, (double)tre, acc_re[q]);
-        acc_im[q] = __builtin_fma(scale, (double)tim, acc_im[q]);
     }
 }
 
 // Radii of a mixed-form lane's slots (panels w0 + po + 4 q, sign sg) in
-// FP64, FP32 and squared.
+// FP32, and their squares in FP32 and FP64.
 template <int PG>
 HSD_HD void mixed_lane_radii(int w0, int po, int sg, double h, double hx, float *rf, float *r2f, double *r2d)
 {
@@ -388,8 +413,8 @@ __device__ __forceinline__ void direct_wave_body(
     // are laid out as (po, sg, k), see consume32
     const int pbase = w0 + g * PG;
     const int po = lane >> 4, sgl = (lane >> 3) & 1;
-    double r2d[F64 ? 1 : NS];
     float rf[F64 ? 1 : NS], r2f[F64 ? 1 : NS];
+    double r2d[F64 ? 1 : NS];
     if constexpr (!F64) mixed_lane_radii<PG>(w0, po, sgl, h, hx, rf, r2f, r2d);
     auto &L = lds[w];
 
@@ -398,8 +423,13 @@ __device__ __forceinline__ void direct_wave_body(
     const int64_t t_begin = ntot * blockIdx.y / K;
     const int64_t t_end = ntot * (blockIdx.y + 1) / K;
 
+    // FP64 form: FP64 tile sums over kTileBatches batches merged into the
+    // running totals; mixed form: the closed branch's FP32 sums over one
+    // batch flushed into the FP64 running totals after every batch (the
+    // series branch adds to the running totals directly, see consume32)
+    using Acc = typename std::conditional<F64, double, float>::type;
     double tot_re[NS], tot_im[NS];
-    double acc_re[NS], acc_im[NS];
+    Acc acc_re[NS], acc_im[NS];
 #pragma unroll
     for (int i = 0; i < NS; ++i) { tot_re[i] = 0.0; tot_im[i] = 0.0; acc_re[i] = 0; acc_im[i] = 0; }
 
@@ -423,22 +453,35 @@ __device__ __forceinline__ void direct_wave_body(
             if constexpr (F64)
                 consume64<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][g * PG], h, hx, pbase, acc_re, acc_im);
             else
-                consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1, acc_re, acc_im);
+                consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1, acc_re, acc_im, tot_re,
+                              tot_im);
         }
         wave_lds_sync();
-        if (++nb == kTileBatches) {
-            nb = 0;
+        if constexpr (F64) {
+            if (++nb == kTileBatches) {
+                nb = 0;
+#pragma unroll
+                for (int i = 0; i < NS; ++i) {
+                    tot_re[i] += acc_re[i];
+                    tot_im[i] += acc_im[i];
+                    acc_re[i] = 0.0;
+                    acc_im[i] = 0.0;
+                }
+            }
+        } else {
 #pragma unroll
             for (int i = 0; i < NS; ++i) {
-                tot_re[i] += acc_re[i];
-                tot_im[i] += acc_im[i];
-                acc_re[i] = 0.0;
-                acc_im[i] = 0.0;
+                tot_re[i] += (double)acc_re[i];
+                tot_im[i] += (double)acc_im[i];
+                acc_re[i] = 0.0f;
+                acc_im[i] = 0.0f;
             }
         }
     }
+    if constexpr (F64) {
 #pragma unroll
-    for (int i = 0; i < NS; ++i) { tot_re[i] += acc_re[i]; tot_im[i] += acc_im[i]; }
+        for (int i = 0; i < NS; ++i) { tot_re[i] += acc_re[i]; tot_im[i] += acc_im[i]; }
+    }
     if (!valid) return;
     double2 *out = partial + (int64_t)blockIdx.y * N + d * (int64_t)(P * 2 * kNH);
 #pragma unroll
@@ -547,6 +590,7 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
         const int w0 = wi * kNH * PG;
         std::vector<double> tre(64 * NS, 0.0), tim(64 * NS, 0.0);
         std::vector<double> are(64 * NS, 0.0), aim(64 * NS, 0.0);
+        std::vector<float> fre(64 * NS, 0.0f), fim(64 * NS, 0.0f);
         int nb = 0;
         for (int64_t tb = 0; tb < nA; tb += kTB) {
             const int nvalid = (int)std::min<int64_t>(kTB, nA - tb);
@@ -573,8 +617,8 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
                 const int k = lane & 7, g = lane >> 3;
                 const int pbase = w0 + g * PG;
                 const int po = lane >> 4, sgl = (lane >> 3) & 1;
-                double r2d[NS];
                 float rf[NS], r2f[NS];
+                double r2d[NS];
                 mixed_lane_radii<PG>(w0, po, sgl, h, hx_tab[k], rf, r2f, r2d);
                 for (int t = 0; t < nvalid; ++t) {
                     if (F64) {
@@ -583,17 +627,18 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
                                       &are[lane * NS], &aim[lane * NS]);
                     } else {
                         auto &L = b32[0];
-                        consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1,
-                                      &are[lane * NS], &aim[lane * NS]);
+                        consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1, &fre[lane * NS],
+                                      &fim[lane * NS], &tre[lane * NS], &tim[lane * NS]);
                     }
                 }
             }
-            if (++nb == kTileBatches) {
+            if (!F64 || ++nb == kTileBatches) {
                 nb = 0;
                 for (int i = 0; i < 64 * NS; ++i) {
-                    tre[i] += are[i];
-                    tim[i] += aim[i];
+                    tre[i] += F64 ? are[i] : (double)fre[i];
+                    tim[i] += F64 ? aim[i] : (double)fim[i];
                     are[i] = aim[i] = 0.0;
+                    fre[i] = fim[i] = 0.0f;
                 }
             }
         }

@@ -145,6 +145,66 @@ def test_distance_levels_against_stored_oracle(hsd_ctx, orc):
     assert all(3.8 < r < 4.2 for r in ratios), ratios
 
 
+def test_mixed_form_levels_against_stored_oracle(hsd_ctx):
+    """The mixed form against the FP64 oracle's d2 at levels 2-7 on the
+    262,144-node rule: within the error the library states for it at every
+    level, and within 1e-7 relative at level 7 (its target)."""
+    path = golden_path("small_rule_levels.json")
+    if not os.path.exists(path):
+        pytest.skip("fixture not generated")
+    gold = json.load(open(path))
+    g = hsd.Rule.spherical_product(hsd_ctx, **{k: gold["rule"][k] for k in SMALL})
+    rel = {}
+    for L in range(2, 8):
+        if str(L) not in gold["d2"]:
+            continue
+        ref = gold["d2"][str(L)]
+        v, f = icosphere(L)
+        mesh = hsd.Mesh(hsd_ctx, v, f)
+        res = hsd.distance(hsd_ctx, mesh, None, g, hsd.Params(s=gold["s"], form="mixed"))
+        rel[L] = (res.d2 - ref) / ref
+        print(f"level {L} mixed: gpu {res.d2!r} oracle {ref!r} rel {rel[L]:+.2e} (stated {res.rel_err_stated:.0e})")
+        stated = res.rel_err_stated
+        mesh.close()
+    g.close()
+    assert all(abs(e) <= stated for e in rel.values()), rel
+    if 7 in rel:
+        assert abs(rel[7]) <= 1e-7
+
+
+def test_large_rule_levels_and_convergence(hsd_ctx):
+    """Levels 3-7 on the 8,388,608-node rule (r <= 256: 16 panels x 16
+    radial x 128 x 256): FP64 d2 within 1e-10 of the oracle's stored values
+    where the oracle ran (levels 3-5), the mixed form within 1e-7 there, and
+    the ratio of d = sqrt(d2) per level over levels 3-7 near 4 (the
+    quadratic convergence of section 4.2, Fig. 3(b))."""
+    path = golden_path("large_rule_levels.json")
+    if not os.path.exists(path):
+        pytest.skip("fixture not generated")
+    gold = json.load(open(path))
+    g = hsd.Rule.spherical_product(hsd_ctx, **gold["rule"])
+    d = {}
+    for L in range(3, 8):
+        v, f = icosphere(L)
+        mesh = hsd.Mesh(hsd_ctx, v, f)
+        res = hsd.distance(hsd_ctx, mesh, None, g, hsd.Params(s=gold["s"]))
+        d[L] = res.d2
+        ref = gold["d2"].get(str(L))
+        if ref is not None:
+            mixed = hsd.distance(hsd_ctx, mesh, None, g, hsd.Params(s=gold["s"], form="mixed")).d2
+            print(f"large rule level {L}: gpu {res.d2!r} oracle {ref!r} rel {abs(res.d2 - ref) / ref:.2e}, "
+                  f"mixed rel {abs(mixed - ref) / ref:.2e}")
+            assert abs(res.d2 - ref) <= 1e-10 * ref
+            assert abs(mixed - ref) <= 1e-7 * ref
+        else:
+            print(f"large rule level {L}: gpu {res.d2!r} (no oracle value)")
+        mesh.close()
+    ratios = [math.sqrt(d[a] / d[a + 1]) for a in range(3, 7)]
+    print("large rule: d ratios levels 3-7", ["%.4f" % q for q in ratios])
+    assert all(3.8 < q < 4.2 for q in ratios), ratios
+    g.close()
+
+
 @pytest.mark.parametrize("name,spec_key", [("level7_small_rule_sampled", "small"),
                                            ("level7_large_rule_sampled", "large")])
 def test_level7_sampled_nodes(hsd_ctx, name, spec_key):
@@ -187,6 +247,27 @@ def test_mesh_vs_mesh_and_empty(hsd_ctx, orc):
     res0 = hsd.distance(hsd_ctx, empty, None, g)
     ref0 = orc.distance(np.zeros((0, 3)), np.zeros((0, 3), np.int32), o)
     assert res0.d2 == pytest.approx(ref0, rel=1e-13)
+
+
+@pytest.mark.parametrize("form,tol", [("fp64", 1e-10), ("mixed", 1e-6)])
+def test_mesh_vs_mesh_wave_kernel(hsd_ctx, orc, form, tol):
+    """Mesh against mesh on a rule with 16-node panels (the wave-per-direction
+    kernel), where the second mesh's triangles enter with J < 0."""
+    rng = np.random.default_rng(10)
+    spec = dict(r_max=32.0, n_panels=8, n_per_panel=16, n_cos=8, n_phi=16)
+    g, o = _rules(hsd_ctx, orc, spec)
+    v1, f1 = icosphere(2)
+    v1 = rotate(perturb_radial(v1, 0.02, rng), random_rotation(rng))
+    v2, f2 = icosphere(1)
+    v2 = rotate(v2, random_rotation(rng)) * 1.02
+    m1, m2 = hsd.Mesh(hsd_ctx, v1, f1), hsd.Mesh(hsd_ctx, v2, f2)
+    res = hsd.distance(hsd_ctx, m1, m2, g, hsd.Params(form=form))
+    ref = orc.distance(v1, f1, o, verts2=v2, tris2=f2)
+    print(f"mesh vs mesh, 16-node panels, {form}: gpu {res.d2!r} oracle {ref!r} rel {abs(res.d2 - ref) / ref:.2e}")
+    assert abs(res.d2 - ref) <= tol * ref
+    m1.close()
+    m2.close()
+    g.close()
 
 
 def test_deterministic_and_split_invariant(hsd_ctx):
