@@ -124,6 +124,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run a plain device copy of this many MiB (reference kernel for "
@@ -282,13 +283,46 @@ def main():
                                                      n_cos=32, n_phi=64),
                  "large": rule}
         out["serving"] = {"trace": f"{len(trace)} requests, Poisson 20/s, seed 0, levels 1-6, 30% "
-                                   "mesh-vs-mesh, 1% on the large rule", "slots": 4}
+                                   "mesh-vs-mesh, 1% on the large rule", "slots": 4,
+                          "note": "saturated: the same requests all submitted at t = 0 (capacity); "
+                                  "offered_load = the trace's pairs per second of arrivals / the "
+                                  "saturated pairs per second; device_busy_frac = share of the span "
+                                  "with at least one request admitted"}
         for form in ("fp64", "mixed"):
+            prm = hsd.Params(s=1.0, form=form)
             with hsd.Server(ctx, slots=4, chunk_pairs=20_000_000_000) as srv:
-                st = replay(srv, trace, rules, hsd.Params(s=1.0, form=form))
-            st.pop("results")
+                sat = replay(srv, trace, rules, prm, time_scale=0.0)
+            with hsd.Server(ctx, slots=4, chunk_pairs=20_000_000_000) as srv:
+                st = replay(srv, trace, rules, prm, capacity_pairs_per_s=sat["pairs_per_s"])
+            for x in (sat, st):
+                x.pop("results")
+            st["saturated"] = {k: sat[k] for k in ("distances_per_s", "pairs_per_s", "span_s", "p50_ms",
+                                                   "p99_ms", "failed", "device_busy_frac")}
             out["serving"][form] = st
-            _progress(f"serving {form}: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms")
+            _progress(f"serving {form}: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, load "
+                      f"{st.get('offered_load', float('nan')):.2f}; saturated {sat['distances_per_s']:.1f}/s")
+    if not args.no_sweep:
+        # per-request device time of the direct sum by mesh level, rule and
+        # form: the service times behind the serving trace's latencies
+        rules_sw = {"small": hsd.Rule.spherical_product(ctx, r_max=64.0, n_panels=8, n_per_panel=16,
+                                                        n_cos=32, n_phi=64), "large": rule}
+        sweep = {}
+        for rname, rl in rules_sw.items():
+            for level in range(1, 7):
+                vs, fs = icosphere(level)
+                ms = hsd.Mesh(ctx, vs, fs)
+                row = {}
+                for form in ("fp64", "mixed"):
+                    prm = hsd.Params(s=1.0, form=form)
+                    hsd.distance(ctx, ms, None, rl, prm)
+                    row[form + "_ms"] = float(np.median([hsd.distance(ctx, ms, None, rl, prm).transform_ms
+                                                         for _ in range(3)]))
+                row["mixed_speedup"] = row["fp64_ms"] / row["mixed_ms"]
+                sweep[f"{rname}-L{level}"] = row
+                ms.close()
+        rules_sw["small"].close()
+        out["kernel_ms_by_level"] = sweep
+        _progress("sweep " + ", ".join(f"{k} {v['mixed_speedup']:.2f}x" for k, v in sweep.items()))
     if not args.no_cpu:
         import oracle
         orule = oracle.spherical_product_rule(**spec)

@@ -5,7 +5,7 @@ import ctypes as C
 import os
 import threading
 
-from ._build import LIB
+from ._build import LIB, TEST_LIB
 
 HSD_OK, HSD_PENDING = 0, 1
 HSD_EINVAL, HSD_ENOMEM, HSD_EDEVICE, HSD_EAGAIN, HSD_ECANCELED, HSD_ENOTFOUND = -1, -2, -3, -4, -5, -6
@@ -108,27 +108,38 @@ SIGNATURES = {
     "hsd_server_destroy": (None, [C.c_void_p]),
 }
 
-_lib = None
+_libs = {}
 _lock = threading.Lock()
+
+
+def _open(p: str):
+    if not os.path.exists(p):
+        raise RuntimeError(
+            f"{p} is missing: the HIP library has not been built "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
 
 
 def load(path: str | None = None):
     """Load libhsd.so; raises if it has not been built (there is no fallback)."""
-    global _lib
+    p = path or LIB
     with _lock:
-        if _lib is None:
-            p = path or LIB
-            if not os.path.exists(p):
-                raise RuntimeError(
-                    f"{p} is missing: the HIP library has not been built "
-                    "(python -c 'import __graft_entry__ as g; g.build()')")
-            L = C.CDLL(p)
-            for name, (res, args) in SIGNATURES.items():
-                f = getattr(L, name)
-                f.restype = res
-                f.argtypes = args
-            _lib = L
-    return _lib
+        if p not in _libs:
+            _libs[p] = _open(p)
+    return _libs[p]
+
+
+def load_test_hooks():
+    """libhsd_testhooks.so: the same library built with the test hooks (CPU
+    runs of the lane bodies, the FFT on its own, the simulated serving
+    executor).  For tests only; objects created through one library must
+    not be passed to the other."""
+    return load(TEST_LIB)
 
 
 def exported_symbols() -> list[str]:

@@ -367,7 +367,8 @@ class Server:
     def __init__(self, ctx: Context | None, slots: int = 4, queue_capacity: int = 4096,
                  budget_bytes: int = 64 << 30, chunk_pairs: int = 20_000_000_000, _fake_rate: float | None = None):
         self.ctx = ctx
-        self._lib = L.load()
+        # the simulated executor lives in the test-hooks build of the library
+        self._lib = L.load() if _fake_rate is None else L.load_test_hooks()
         cfg = L.ServerCfg()
         cfg.slots, cfg.queue_capacity = int(slots), int(queue_capacity)
         cfg.hbm_budget_bytes, cfg.chunk_pairs = int(budget_bytes), int(chunk_pairs)

@@ -388,6 +388,7 @@ hsd_status launch_gather(hipStream_t st, const hsd_mesh *m, const double *tri_gr
 
 } // namespace hsd
 
+#ifdef HSD_TEST_HOOKS
 using namespace hsd;
 
 extern "C" {
@@ -429,3 +430,4 @@ void hsd__host_pair_grad(double thmid, double a, double b, double tau, double *o
 }
 
 } // extern "C"
+#endif // HSD_TEST_HOOKS

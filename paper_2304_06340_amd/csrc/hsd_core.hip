@@ -522,6 +522,7 @@ hsd_status hsd_create_surface_measure(hsd_ctx *ctx, const hsd_surface_desc *d, h
     return hsd_create_point_measure(ctx, pts.data(), w.data(), (int64_t)w.size(), HSD_MEM_HOST, out);
 }
 
+#ifdef HSD_TEST_HOOKS
 // Host test hook: the quadrature of a built-in surface (n_u * n_v points).
 int hsd__host_surface_points(const hsd_surface_desc *d, double *pts, double *w)
 {
@@ -531,6 +532,7 @@ int hsd__host_surface_points(const hsd_surface_desc *d, double *pts, double *w)
     std::memcpy(w, ww.data(), ww.size() * 8);
     return 0;
 }
+#endif // HSD_TEST_HOOKS
 
 hsd_status hsd_create_point_measure(hsd_ctx *ctx, const double *points, const double *weights, int64_t n,
                                     int32_t mem_kind, hsd_mesh **out)
@@ -650,6 +652,48 @@ hsd_status create_mesh_on(hsd_ctx *ctx, hipStream_t st, const double *verts, int
     if (nt) HSD_HIP_TRY(hipMemcpyAsync(m->csr_ent.ptr, ent.data(), (size_t)nt * 12, hipMemcpyHostToDevice, st));
     HSD_HIP_TRY(hipStreamSynchronize(st));
     *out = m.release();
+    return HSD_OK;
+}
+
+// Reload a mesh object that a serving slot owns with new vertices and
+// triangles: validated as create_mesh_on does, but only the triangle
+// records go to the device (a slot evaluates distances, not gradients), into
+// the mesh's record buffer when it is large enough (no allocation, and so no
+// free, which would wait for the whole device, between requests).  rec is
+// the host staging buffer of the copy on st; the caller keeps it unchanged
+// until that copy has completed.
+hsd_status mesh_reload(hsd_ctx *ctx, hipStream_t st, hsd_mesh *m, const double *verts, int64_t nv,
+                       const int32_t *tris, int64_t nt, std::vector<TriRec> &rec)
+{
+    if (nv < 0 || nt < 0 || nv > INT32_MAX || nt > INT32_MAX / 3) {
+        set_error("bad mesh sizes nv=%lld nt=%lld", (long long)nv, (long long)nt);
+        return HSD_EINVAL;
+    }
+    double extent = 0.0;
+    for (int64_t i = 0; i < nv * 3; ++i) {
+        if (!std::isfinite(verts[i])) {
+            set_error("vertex %lld is not finite", (long long)(i / 3));
+            return HSD_EINVAL;
+        }
+        extent = std::max(extent, std::fabs(verts[i]));
+    }
+    for (int64_t i = 0; i < nt * 3; ++i)
+        if (tris[i] < 0 || tris[i] >= nv) {
+            set_error("triangle %lld: vertex index %d outside [0, %lld)", (long long)(i / 3), tris[i], (long long)nv);
+            return HSD_EINVAL;
+        }
+    rec.resize((size_t)nt);
+    build_tri_records(verts, tris, nt, rec.data());
+    const size_t need = (size_t)nt * sizeof(TriRec);
+    if (m->tris.bytes < need) {
+        hsd_status stt = m->tris.alloc(ctx, need);
+        if (stt != HSD_OK) return stt;
+    }
+    if (nt) HSD_HIP_TRY(hipMemcpyAsync(m->tris.ptr, rec.data(), need, hipMemcpyHostToDevice, st));
+    m->nv = nv;
+    m->nt = nt;
+    m->extent = extent;
+    m->point_measure = false;
     return HSD_OK;
 }
 

@@ -668,6 +668,7 @@ hsd_status launch_sum_partials(hipStream_t st, const double2 *partial, int K, in
 
 } // namespace hsd
 
+#ifdef HSD_TEST_HOOKS
 // ---------------------------------------------------------------------------
 // Host-side self checks: the same lane bodies run on the CPU (not part of the
 // public ABI; used by the library's CPU tests, small inputs only).
@@ -775,3 +776,4 @@ void hsd__host_sincos32(const double *x, int64_t n, float *c, float *s)
 }
 
 } // extern "C"
+#endif // HSD_TEST_HOOKS

@@ -572,6 +572,7 @@ hsd_status launch_direct_wave(hipStream_t st, const MeshPair &mp, const hsd_rule
                               : launch_wave_pg<1>(st, mp, rule, form, tau, K, d_begin, d_count, partial);
 }
 
+#ifdef HSD_TEST_HOOKS
 // ---------------------------------------------------------------------------
 // host emulation of one direction (self checks)
 // ---------------------------------------------------------------------------
@@ -663,9 +664,11 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
 }
 
 void build_tri_records(const double *verts, const int32_t *tris, int64_t nt, TriRec *rec);
+#endif // HSD_TEST_HOOKS
 
 } // namespace hsd
 
+#ifdef HSD_TEST_HOOKS
 extern "C" {
 
 // mu^ at every node of a spherical product rule (n = 16 per panel, P a
@@ -694,3 +697,4 @@ int hsd__host_transform_wave(const double *verts, const int32_t *tris, int64_t n
 }
 
 } // extern "C"
+#endif // HSD_TEST_HOOKS

@@ -305,6 +305,7 @@ hsd_status fft3d_forward(hipStream_t st, const FftPlan &p, double2 *data, int e_
 
 } // namespace hsd
 
+#ifdef HSD_TEST_HOOKS
 extern "C" {
 
 // Test hook (not part of the public ABI): forward 3-D FFT of a host cube
@@ -331,3 +332,4 @@ int hsd__test_fft3d_pruned(hsd_ctx *ctx, double *host_data, int n, int e_in, int
 int hsd__test_fft3d(hsd_ctx *ctx, double *host_data, int n) { return hsd__test_fft3d_pruned(ctx, host_data, n, 0, 0); }
 
 } // extern "C"
+#endif // HSD_TEST_HOOKS

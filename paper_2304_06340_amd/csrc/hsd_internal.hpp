@@ -86,6 +86,8 @@ struct NufftScratch {
     std::unique_ptr<FftPlan> plan;
     NufftScratch();
     ~NufftScratch();
+    size_t bytes() const;    // device bytes held
+    void release();          // free them all
 };
 
 } // namespace hsd
@@ -203,6 +205,8 @@ hsd_status launch_direct_gen_range(hipStream_t st, const MeshPair &mp, const dou
                                    int64_t i_count, double2 *partial);
 hsd_status create_mesh_on(hsd_ctx *ctx, hipStream_t st, const double *verts, int64_t nv, const int32_t *tris,
                           int64_t nt, int32_t mem_kind, hsd_mesh **out, const double *point_weights = nullptr);
+hsd_status mesh_reload(hsd_ctx *ctx, hipStream_t st, hsd_mesh *m, const double *verts, int64_t nv,
+                       const int32_t *tris, int64_t nt, std::vector<TriRec> &rec);
 hsd_status launch_finalize(hipStream_t st, const hsd_rule *rule, const double *wtab,
                            const double *nutab, const double2 *partial, int K, int64_t n,
                            bool sphere_target, double2 *resid_out, double *block_out,
@@ -231,6 +235,10 @@ hsd_status launch_gather(hipStream_t st, const hsd_mesh *m, const double *tri_gr
                          double *grad);
 
 // NUFFT (hsd_nufft.hip).
+// Device bytes one transform of ntri triangles' points (sources within X of
+// the origin per axis) on `rule` allocates, including the rule's cached
+// per-node tables on first use; -1 if the grid is not supported.
+int64_t nufft_footprint(double X, const hsd_rule *rule, const hsd_params *p, int64_t ntri);
 hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc,
                                 const hsd_mesh *mu, const hsd_mesh *nu, const hsd_rule *rule,
                                 const hsd_params *p, double2 *out, double *pairs);

@@ -635,21 +635,40 @@ static double es_ft_host(const std::vector<double2> &tab, double k)
 NufftScratch::NufftScratch() = default;
 NufftScratch::~NufftScratch() = default;
 
-hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, const hsd_mesh *mu,
-                                const hsd_mesh *nu, const hsd_rule *rule, const hsd_params *p, double2 *out,
-                                double *pairs)
+size_t NufftScratch::bytes() const
 {
-    hsd_status stt;
+    size_t b = 0;
+    for (const DevBuf *x : {&pts, &spts, &keys, &keys2, &iota, &offs, &perm, &sorttmp, &grid1, &fine, &tri, &ftq,
+                            &hinv, &titems, &tstart, &itile, &tilebuf, &scantmp})
+        b += x->bytes;
+    if (plan) b += plan->tw.bytes + plan->plan.bytes;
+    return b;
+}
+
+void NufftScratch::release()
+{
+    for (DevBuf *x : {&pts, &spts, &keys, &keys2, &iota, &offs, &perm, &sorttmp, &grid1, &fine, &tri, &ftq, &hinv,
+                      &titems, &tstart, &itile, &tilebuf, &scantmp})
+        x->release();
+    plan.reset();
+}
+
+// Grid sizes of one transform: kernel width and shape, source spacing,
+// spread grid n1^3 and FFT grid n2^3 (type 3), or one grid of n1 = n2
+// points per axis with the lattice read-out (type 1).
+struct NufftSizes {
+    bool lattice = false;
+    int w = 0, n1 = 0, n2 = 0;
+    double sigma = 2.0, beta = 0.0, h1 = 0.0;
+};
+
+static hsd_status nufft_sizes(double X, const hsd_rule *rule, const hsd_params *p, NufftSizes &z)
+{
     const double sigma = p->nufft_sigma > 1.0 ? p->nufft_sigma : 2.0;
     int w = p->nufft_width;
     if (w <= 0) w = (int)std::ceil(std::log10(1.0 / std::max(p->nufft_tol, 1e-16))) + 1;
     w = std::max(2, std::min(w, kMaxW));
     const double beta = 0.97 * kPi * (1.0 - 0.5 / sigma) * w;
-    // extent of the sources and of the targets per dimension
-    // (both computed once, when the mesh and the rule were created)
-    double X = 0.0;
-    for (const hsd_mesh *m : {mu, nu})
-        if (m) X = std::max(X, m->extent);
     X = std::max(X, 1e-3);
     const bool sp = rule->kind == HSD_RULE_SPHERICAL_PRODUCT;
     const double S = std::max(sp ? rule->sp.r_max : rule->extent, 1e-3);
@@ -674,6 +693,58 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
         set_error("NUFFT grid %d^3 exceeds the supported FFT size (2048)", n2);
         return HSD_EINVAL;
     }
+    z.lattice = lattice;
+    z.w = w;
+    z.n1 = n1;
+    z.n2 = n2;
+    z.sigma = sigma;
+    z.beta = beta;
+    z.h1 = h1;
+    return HSD_OK;
+}
+
+static int64_t spread_items_bound(int64_t np, int nbins)
+{
+    return nbins + (27 * ((np + kChunk - 1) / kChunk + (int64_t)nbins) + kItemChunks - 1) / kItemChunks;
+}
+
+int64_t nufft_footprint(double X, const hsd_rule *rule, const hsd_params *p, int64_t ntri)
+{
+    NufftSizes z;
+    if (nufft_sizes(X, rule, p, z) != HSD_OK) return -1;
+    const int64_t nq = p->tri_rule == HSD_TRI_GL8X8 ? 64 : 7;
+    const int64_t np = ntri * nq;
+    const int64_t nbx = (z.n1 + kBin - 1) / kBin, nbins = nbx * nbx * nbx;
+    const int64_t items = spread_items_bound(np, (int)nbins);
+    const int64_t N = rule->n_nodes;
+    int64_t b = np * (32 + 32 + 4 * 4)                        // points (raw, sorted), keys, iota, permutation
+                + 2 * np * 4 + 2 * (nbins + 1) * 4 + (1 << 20)   // sort and scan temporaries (bounded)
+                + (nbins + 1) * 4 * 3 + items * 4
+                + items * (int64_t)kBin * kBin * kBin * 8        // partial tiles
+                + (int64_t)z.n1 * z.n1 * z.n1 * 8                 // spread grid
+                + (int64_t)z.n2 * z.n2 * z.n2 * 16                // FFT grid
+                + (int64_t)z.n2 * 16 + 4096 + 64 * 32             // twiddles, stages, small tables
+                + (z.lattice ? 0 : N * 40);                       // the rule's per-node tables (first use)
+    return b;
+}
+
+hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, const hsd_mesh *mu,
+                                const hsd_mesh *nu, const hsd_rule *rule, const hsd_params *p, double2 *out,
+                                double *pairs)
+{
+    hsd_status stt;
+    // extent of the sources (computed once, when the meshes were created)
+    double X = 0.0;
+    for (const hsd_mesh *m : {mu, nu})
+        if (m) X = std::max(X, m->extent);
+    X = std::max(X, 1e-3);
+    NufftSizes z;
+    if ((stt = nufft_sizes(X, rule, p, z)) != HSD_OK) return stt;
+    const bool lattice = z.lattice;
+    const int w = z.w, n1 = z.n1, n2 = z.n2;
+    const double beta = z.beta, h1 = z.h1;
+    const bool sp = rule->kind == HSD_RULE_SPHERICAL_PRODUCT;
+    const double S = std::max(sp ? rule->sp.r_max : rule->extent, 1e-3);   // target extent per axis
     const int nbx = (n1 + kBin - 1) / kBin;
     const int nbins = nbx * nbx * nbx;
     std::vector<double4> trule;
@@ -702,19 +773,21 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
             dec[(size_t)(k + M / 2)] = 2.0 / ((double)w * es_ft_host(ftq, k * kPi * w / n1));
     }
     const int64_t N = rule->n_nodes;
-    if ((stt = sc.tri.alloc(ctx, trule.size() * sizeof(double4))) != HSD_OK) return stt;
-    if ((stt = sc.ftq.alloc(ctx, ftq.size() * sizeof(double2))) != HSD_OK) return stt;
-    if ((stt = sc.hinv.alloc(ctx, (hinv.size() + dec.size()) * sizeof(double))) != HSD_OK) return stt;
+    // grow-only scratch: a reallocation frees first, and hipFree waits for
+    // the whole device (other serving slots included)
+    auto ens = [&](DevBuf &b, size_t bytes) -> hsd_status {
+        if (b.ptr && b.bytes >= bytes) return HSD_OK;
+        return b.alloc(ctx, std::max<size_t>(bytes, 8));
+    };
+    if ((stt = ens(sc.tri, trule.size() * sizeof(double4))) != HSD_OK) return stt;
+    if ((stt = ens(sc.ftq, ftq.size() * sizeof(double2))) != HSD_OK) return stt;
+    if ((stt = ens(sc.hinv, (hinv.size() + dec.size()) * sizeof(double))) != HSD_OK) return stt;
     HSD_HIP_TRY(hipMemcpyAsync(sc.tri.ptr, trule.data(), trule.size() * sizeof(double4), hipMemcpyHostToDevice, st));
     HSD_HIP_TRY(hipMemcpyAsync(sc.ftq.ptr, ftq.data(), ftq.size() * sizeof(double2), hipMemcpyHostToDevice, st));
     HSD_HIP_TRY(hipMemcpyAsync(sc.hinv.ptr, hinv.data(), hinv.size() * sizeof(double), hipMemcpyHostToDevice, st));
     if (!dec.empty())
         HSD_HIP_TRY(hipMemcpyAsync(sc.hinv.as<double>() + hinv.size(), dec.data(), dec.size() * sizeof(double),
                                    hipMemcpyHostToDevice, st));
-    auto ens = [&](DevBuf &b, size_t bytes) -> hsd_status {
-        if (b.ptr && b.bytes >= bytes) return HSD_OK;
-        return b.alloc(ctx, std::max<size_t>(bytes, 8));
-    };
     if ((stt = ens(sc.pts, (size_t)np * sizeof(double4))) != HSD_OK) return stt;
     if ((stt = ens(sc.spts, (size_t)np * sizeof(double4))) != HSD_OK) return stt;
     if ((stt = ens(sc.keys, (size_t)np * sizeof(int))) != HSD_OK) return stt;
@@ -733,8 +806,7 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     // (each tile scans 27 bins of ceil(count / 64) chunks), a bound known
     // without reading anything back
     const int ntiles = nbins;
-    const int64_t max_items =
-        ntiles + (27 * ((np + kChunk - 1) / kChunk + (int64_t)nbins) + kItemChunks - 1) / kItemChunks;
+    const int64_t max_items = spread_items_bound(np, nbins);
     if (max_items > INT32_MAX) {
         set_error("NUFFT: too many spread work items");
         return HSD_EINVAL;

@@ -1,10 +1,10 @@
 // hsd_server.hip -- serving loop: continuous batching of distance requests.
 //
 // Requests are copied at submit and queued (FIFO).  A scheduler thread
-// admits queued requests into free slots while the sum of admitted device
-// footprints stays within the server budget; every slot owns a HIP stream
-// and its scratch buffers, so the work of admitted requests overlaps on the
-// device.  An admitted request's direct sum is enqueued in chunks of
+// admits queued requests into free slots while the device bytes charged to
+// the slots (running requests' footprints, scratch kept by idle slots) stay
+// within the server budget; every slot owns a HIP stream and its scratch
+// buffers, so the work of admitted requests overlaps on the device.  An admitted request's direct sum is enqueued in chunks of
 // directions (a bounded number in flight per slot), so newly admitted
 // requests start within one chunk of the others and a cancelled request
 // stops between chunks.  After the last chunk the slot enqueues the
@@ -14,7 +14,9 @@
 // Per-request arithmetic does not depend on the mix: triangle splits and
 // lane layout are functions of the request alone, chunk boundaries only
 // select which lanes a launch runs, and every reduction has a fixed order,
-// so a result is bitwise the same alone or in any mix.
+// so a result is bitwise the same alone or in any mix.  (The splits are
+// chosen so that each chunk fills the device; they can differ from
+// hsd_distance's, and so can the last bits of a result.)
 //
 // The scheduling core talks to an Executor.  The device executor runs the
 // kernels; a fake executor (CPU only, simulated durations) lets the queue,
@@ -44,7 +46,8 @@ struct Job {
     bool has_nu = false;
     hsd_rule *rule = nullptr;
     hsd_params params{};
-    int64_t footprint = 0;
+    int64_t footprint = 0;        // device bytes the request needs (meshes + scratch)
+    int64_t mesh_bytes = 0;       // of which its meshes (freed when it completes)
     // progress
     int slot = -1;
     int64_t next_chunk = 0, n_chunks = 0;
@@ -62,8 +65,11 @@ struct Job {
 // ---------------------------------------------------------------------------
 struct Executor {
     virtual ~Executor() = default;
+    virtual hsd_status init() { return HSD_OK; }            // streams, events, pinned buffers
     virtual int slots() const = 0;
-    virtual int64_t footprint(const Job &j) = 0;
+    virtual int64_t footprint(Job &j) = 0;                  // sets j.mesh_bytes too
+    virtual int64_t retained(int s) const = 0;               // device bytes slot s keeps between requests
+    virtual void trim(int s) = 0;                            // free them (slot idle)
     virtual hsd_status start(int s, Job &j) = 0;            // upload / plan; sets n_chunks
     virtual hsd_status enqueue_chunk(int s, Job &j) = 0;    // next chunk (j.next_chunk)
     virtual int chunks_done(int s, Job &j) = 0;             // completed chunks so far
@@ -73,11 +79,16 @@ struct Executor {
     virtual void release(int s, Job &j) = 0;
 };
 
+// A slot's device state persists across its requests: the two mesh objects
+// are reloaded per request (their record buffers grow, never shrink), and
+// the chunk events are a pool; nothing is freed between requests, since a
+// free waits for the whole device and would stall the other slots.
 struct DeviceSlot {
     hipStream_t stream = nullptr;
     Scratch partial, nodebuf, redbuf;
     NufftScratch nufft;
     hsd_mesh *mu = nullptr, *nu = nullptr;
+    std::vector<TriRec> stage_mu, stage_nu;   // host staging of the record uploads
     std::vector<hipEvent_t> chunk_ev;
     hipEvent_t ev_begin = nullptr, ev_done = nullptr;
     double *host_result = nullptr;
@@ -91,38 +102,97 @@ struct DeviceExecutor : Executor {
     int64_t chunk_pairs;
     std::vector<DeviceSlot> sl;
 
-    DeviceExecutor(hsd_ctx *c, int n, int64_t cp) : ctx(c), chunk_pairs(cp), sl(n)
+    DeviceExecutor(hsd_ctx *c, int n, int64_t cp) : ctx(c), chunk_pairs(cp), sl(n) {}
+
+    hsd_status init() override
     {
+        HSD_HIP_TRY(hipSetDevice(ctx->device));
         for (auto &s : sl) {
-            (void)hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
-            (void)hipEventCreateWithFlags(&s.ev_begin, hipEventDefault);
-            (void)hipEventCreateWithFlags(&s.ev_done, hipEventDefault);   // timed against ev_begin
-            (void)hipHostMalloc((void **)&s.host_result, 64, hipHostMallocDefault);
+            for (hsd_mesh **m : {&s.mu, &s.nu}) {
+                *m = new hsd_mesh();
+                (*m)->ctx = ctx;
+                ctx_retain(ctx);
+            }
+            HSD_HIP_TRY(hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking));
+            HSD_HIP_TRY(hipEventCreateWithFlags(&s.ev_begin, hipEventDefault));
+            HSD_HIP_TRY(hipEventCreateWithFlags(&s.ev_done, hipEventDefault));   // timed against ev_begin
+            HSD_HIP_TRY(hipHostMalloc((void **)&s.host_result, 64, hipHostMallocDefault));
         }
+        return HSD_OK;
     }
     ~DeviceExecutor() override
     {
         (void)hipSetDevice(ctx->device);
         for (auto &s : sl) {
-            (void)hipStreamSynchronize(s.stream);
+            if (s.stream) (void)hipStreamSynchronize(s.stream);
             for (auto e : s.chunk_ev) (void)hipEventDestroy(e);
             if (s.mu) hsd_mesh_destroy(s.mu);
             if (s.nu) hsd_mesh_destroy(s.nu);
             s.partial.buf.release();
             s.nodebuf.buf.release();
             s.redbuf.buf.release();
-            (void)hipEventDestroy(s.ev_begin);
-            (void)hipEventDestroy(s.ev_done);
-            (void)hipHostFree(s.host_result);
-            (void)hipStreamDestroy(s.stream);
+            s.nufft.release();
+            if (s.ev_begin) (void)hipEventDestroy(s.ev_begin);
+            if (s.ev_done) (void)hipEventDestroy(s.ev_done);
+            if (s.host_result) (void)hipHostFree(s.host_result);
+            if (s.stream) (void)hipStreamDestroy(s.stream);
         }
     }
     int slots() const override { return (int)sl.size(); }
 
+    int64_t retained(int s) const override
+    {
+        const DeviceSlot &d = sl[s];
+        return (int64_t)(d.partial.buf.bytes + d.nodebuf.buf.bytes + d.redbuf.buf.bytes + d.nufft.bytes() +
+                         (d.mu ? d.mu->tris.bytes : 0) + (d.nu ? d.nu->tris.bytes : 0));
+    }
+
+    void trim(int s) override
+    {
+        DeviceSlot &d = sl[s];
+        (void)hipSetDevice(ctx->device);
+        (void)hipStreamSynchronize(d.stream);
+        d.partial.buf.release();
+        d.nodebuf.buf.release();
+        d.redbuf.buf.release();
+        d.nufft.release();
+        if (d.mu) d.mu->tris.release();
+        if (d.nu) d.nu->tris.release();
+    }
+
     static int64_t n_dirs(const hsd_rule *r) { return r->kind == HSD_RULE_SPHERICAL_PRODUCT ? r->n_dir : r->n_nodes; }
     static int64_t nodes_per_dir(const hsd_rule *r) { return r->kind == HSD_RULE_SPHERICAL_PRODUCT ? r->n_rad : 1; }
 
+    // Directions per chunk: chunk_pairs worth of pairs (the NUFFT: one chunk).
+    int64_t chunk_dirs_of(const Job &j) const
+    {
+        if (j.params.method == HSD_METHOD_NUFFT3) return n_dirs(j.rule);
+        const int64_t pairs_per_dir = (int64_t)(j.t1.size() + j.t2.size()) / 3 * nodes_per_dir(j.rule);
+        const int64_t cd = std::max<int64_t>(1, chunk_pairs / std::max<int64_t>(pairs_per_dir, 1));
+        return std::min<int64_t>(cd, n_dirs(j.rule));
+    }
+
+    // Triangle splits of a request: at least hsd_distance's, and enough that
+    // one chunk's launch has about 4096 waves (a full MI355X at 4 waves per
+    // SIMD) so that a chunk fills the device, with blocks short enough that
+    // other slots' kernels get compute units between them.  A function of
+    // the request alone, so results do not depend on the mix.
     int k_of(const Job &j) const
+    {
+        if (j.params.method == HSD_METHOD_NUFFT3) return 1;
+        const int64_t nt = (int64_t)(j.t1.size() + j.t2.size()) / 3;
+        int K = k_direct(j);
+        if (j.params.k_splits > 0) return K;   // the caller's choice
+        if (j.rule->kind == HSD_RULE_SPHERICAL_PRODUCT && nt > 0) {
+            const int64_t waves_per_dir = std::max<int64_t>(1, wave_count(j.rule) / std::max<int64_t>(j.rule->n_dir, 1));
+            const int64_t cw = chunk_dirs_of(j) * (wave_kernel_applies(j.rule) ? waves_per_dir : 1);
+            const int64_t want = ((int64_t)ctx->num_cu * 16 + cw - 1) / cw;
+            K = (int)std::max<int64_t>(K, std::min<int64_t>({want, 64, std::max<int64_t>(1, nt / 64)}));
+        }
+        return K;
+    }
+
+    int k_direct(const Job &j) const
     {
         const int64_t nt = (int64_t)(j.t1.size() + j.t2.size()) / 3;
         return j.rule->kind == HSD_RULE_SPHERICAL_PRODUCT
@@ -130,39 +200,56 @@ struct DeviceExecutor : Executor {
                    : choose_k_splits_gen(j.rule->n_nodes, nt, ctx->num_cu, j.params.k_splits);
     }
 
-    int64_t footprint(const Job &j) override
+    // Device bytes a request needs on its slot: its meshes (records, indices,
+    // vertices, adjacency), the partial transforms, the reduction partials,
+    // and for the NUFFT method the whole transform plan (points, sort and
+    // scan temporaries, spread tiles, spread grid, FFT grid, twiddles, the
+    // rule's per-node tables).
+    int64_t footprint(Job &j) override
     {
         const int64_t nt = (int64_t)(j.t1.size() + j.t2.size()) / 3;
         const int64_t nv = (int64_t)(j.v1.size() + j.v2.size()) / 3;
         const int64_t N = j.rule->n_nodes;
         const int64_t mesh = nt * (int64_t)(sizeof(TriRec) + 24) + nv * 28 + 8;
-        return mesh + (int64_t)k_of(j) * N * 16 + (N / 256 + 2) * 8;
+        j.mesh_bytes = mesh;
+        const int64_t red = (N / 256 + 2) * 8;
+        if (j.params.method == HSD_METHOD_NUFFT3) {
+            double X = 0.0;
+            for (double x : j.v1) X = std::max(X, std::fabs(x));
+            for (double x : j.v2) X = std::max(X, std::fabs(x));
+            const int64_t plan = nufft_footprint(X, j.rule, &j.params, nt);
+            if (plan < 0) return INT64_MAX;
+            return mesh + N * 16 + red + plan;
+        }
+        return mesh + (int64_t)k_of(j) * N * 16 + red;
     }
+
+    const hsd_mesh *nu_of(const DeviceSlot &d, const Job &j) const { return j.has_nu ? d.nu : nullptr; }
 
     hsd_status start(int s, Job &j) override
     {
         DeviceSlot &d = sl[s];
         hsd_status st;
         HSD_HIP_TRY(hipSetDevice(ctx->device));
-        if ((st = create_mesh_on(ctx, d.stream, j.v1.data(), (int64_t)j.v1.size() / 3, j.t1.data(),
-                                 (int64_t)j.t1.size() / 3, HSD_MEM_HOST, &d.mu)) != HSD_OK)
+        if ((st = mesh_reload(ctx, d.stream, d.mu, j.v1.data(), (int64_t)j.v1.size() / 3, j.t1.data(),
+                              (int64_t)j.t1.size() / 3, d.stage_mu)) != HSD_OK)
             return st;
-        if (j.has_nu && (st = create_mesh_on(ctx, d.stream, j.v2.data(), (int64_t)j.v2.size() / 3, j.t2.data(),
-                                             (int64_t)j.t2.size() / 3, HSD_MEM_HOST, &d.nu)) != HSD_OK)
+        if (j.has_nu && (st = mesh_reload(ctx, d.stream, d.nu, j.v2.data(), (int64_t)j.v2.size() / 3, j.t2.data(),
+                                          (int64_t)j.t2.size() / 3, d.stage_nu)) != HSD_OK)
             return st;
         const double *w = nullptr, *nuv = nullptr;
         if ((st = rule_tables(j.rule, &j.params, d.stream, &w, &nuv)) != HSD_OK) return st;
+        // the NUFFT writes one transform per node (no triangle splits)
         d.K = k_of(j);
         const int64_t N = j.rule->n_nodes;
         if ((st = d.partial.ensure(ctx, (size_t)d.K * N * sizeof(double2))) != HSD_OK) return st;
-        const int64_t pairs_per_dir = (int64_t)(j.t1.size() + j.t2.size()) / 3 * nodes_per_dir(j.rule);
-        int64_t cd = std::max<int64_t>(1, chunk_pairs / std::max<int64_t>(pairs_per_dir, 1));
-        if (j.params.method == HSD_METHOD_NUFFT3) cd = n_dirs(j.rule);   // one chunk
-        d.chunk_dirs = std::min<int64_t>(cd, n_dirs(j.rule));
+        d.chunk_dirs = chunk_dirs_of(j);
         j.n_chunks = (n_dirs(j.rule) + d.chunk_dirs - 1) / d.chunk_dirs;
-        for (auto e : d.chunk_ev) (void)hipEventDestroy(e);
-        d.chunk_ev.assign((size_t)j.n_chunks, nullptr);
-        for (auto &e : d.chunk_ev) HSD_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        while ((int64_t)d.chunk_ev.size() < j.n_chunks) {
+            hipEvent_t e = nullptr;
+            HSD_HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            d.chunk_ev.push_back(e);
+        }
         HSD_HIP_TRY(hipEventRecord(d.ev_begin, d.stream));
         return HSD_OK;
     }
@@ -177,13 +264,13 @@ struct DeviceExecutor : Executor {
         MeshPair mp;
         mp.A = d.mu->tris.as<const TriRec>();
         mp.nA = d.mu->nt;
-        if (d.nu) { mp.B = d.nu->tris.as<const TriRec>(); mp.nB = d.nu->nt; }
+        if (j.has_nu) { mp.B = d.nu->tris.as<const TriRec>(); mp.nB = d.nu->nt; }
         hsd_status st = HSD_OK;
         const int64_t N = j.rule->n_nodes;
         if (j.params.method == HSD_METHOD_NUFFT3) {
             double pairs = 0;
-            st = nufft_transform_rule(ctx, d.stream, d.nufft, d.mu, d.nu, j.rule, &j.params, d.partial.buf.as<double2>(),
-                                      &pairs);
+            st = nufft_transform_rule(ctx, d.stream, d.nufft, d.mu, nu_of(d, j), j.rule, &j.params,
+                                      d.partial.buf.as<double2>(), &pairs);
             j.result.pairs = pairs;
         } else if (mp.nA + mp.nB == 0) {
             HSD_HIP_TRY(hipMemsetAsync(d.partial.buf.ptr, 0, (size_t)N * sizeof(double2), d.stream));
@@ -228,7 +315,7 @@ struct DeviceExecutor : Executor {
         const int64_t nb = finalize_blocks(N);
         if ((st = d.redbuf.ensure(ctx, (size_t)(nb + 1) * sizeof(double))) != HSD_OK) return st;
         const int K = j.params.method == HSD_METHOD_NUFFT3 ? 1 : d.K;
-        const bool empty = j.params.method != HSD_METHOD_NUFFT3 && d.mu->nt + (d.nu ? d.nu->nt : 0) == 0;
+        const bool empty = j.params.method != HSD_METHOD_NUFFT3 && d.mu->nt + (j.has_nu ? d.nu->nt : 0) == 0;
         if ((st = launch_finalize(d.stream, j.rule, w, nuv, d.partial.buf.as<const double2>(), empty ? 1 : K, N,
                                   !j.has_nu, nullptr, d.redbuf.buf.as<double>(), nb)) != HSD_OK)
             return st;
@@ -249,20 +336,19 @@ struct DeviceExecutor : Executor {
         j.result.d2 = d.host_result[0];
         j.result.device_ms = (double)ms;
         if (j.params.method != HSD_METHOD_NUFFT3)
-            j.result.pairs = (double)(d.mu->nt + (d.nu ? d.nu->nt : 0)) * (double)j.rule->n_nodes;
+            j.result.pairs = (double)(d.mu->nt + (j.has_nu ? d.nu->nt : 0)) * (double)j.rule->n_nodes;
         j.result.rel_err_stated = stated_rel_err(&j.params, d.mu->nt);
         return HSD_OK;
     }
 
     void release(int s, Job &) override
     {
-        DeviceSlot &d = sl[s];
-        (void)hipStreamSynchronize(d.stream);
-        if (d.mu) { hsd_mesh_destroy(d.mu); d.mu = nullptr; }
-        if (d.nu) { hsd_mesh_destroy(d.nu); d.nu = nullptr; }
+        // the slot's work has completed (or been drained); its buffers stay
+        (void)hipStreamSynchronize(sl[s].stream);
     }
 };
 
+#ifdef HSD_TEST_HOOKS
 // CPU-only executor for tests of the scheduling logic: a chunk "runs" for
 // pairs / rate seconds of wall time after it is enqueued; the result is a
 // deterministic function of the inputs; tag == -13 makes finish fail.
@@ -278,10 +364,13 @@ struct FakeExecutor : Executor {
     int64_t n_nodes_fake;
     FakeExecutor(int n, double r, int64_t cp) : sl(n), rate(r), chunk_pairs(cp), n_nodes_fake(1000) {}
     int slots() const override { return (int)sl.size(); }
-    int64_t footprint(const Job &j) override
+    int64_t footprint(Job &j) override
     {
-        return (int64_t)(j.t1.size() + j.t2.size()) / 3 * 80 + (int64_t)(j.v1.size() + j.v2.size()) * 8 + 1024;
+        j.mesh_bytes = (int64_t)(j.t1.size() + j.t2.size()) / 3 * 80 + (int64_t)(j.v1.size() + j.v2.size()) * 8;
+        return j.mesh_bytes + 1024;
     }
+    int64_t retained(int) const override { return 0; }
+    void trim(int) override {}
     hsd_status start(int s, Job &j) override
     {
         const int64_t pairs = (int64_t)(j.t1.size() + j.t2.size()) / 3 * n_nodes_fake;
@@ -327,6 +416,8 @@ struct FakeExecutor : Executor {
     void release(int s, Job &) override { sl[s].finishing = false; }
 };
 
+#endif // HSD_TEST_HOOKS
+
 } // namespace hsd
 
 using namespace hsd;
@@ -341,6 +432,11 @@ struct hsd_server {
     std::vector<std::shared_ptr<Job>> active;   // per slot
     std::unordered_map<uint64_t, std::shared_ptr<Job>> jobs;
     uint64_t next_ticket = 1;
+    // Device bytes charged per slot: an idle slot is charged the scratch it
+    // keeps between requests, a busy one the larger of its request's
+    // footprint and that scratch plus the request's meshes (the scratch is
+    // reused, grown if needed); the sum stays within cfg.hbm_budget_bytes.
+    std::vector<int64_t> charge;
     int64_t admitted_bytes = 0;
     bool stop = false;
     std::thread th;
@@ -358,13 +454,35 @@ struct hsd_server {
         done_cv.notify_all();
     }
 
+    void set_charge(int s, int64_t c)
+    {
+        admitted_bytes += c - charge[s];
+        charge[s] = c;
+    }
+
     void free_slot(int s)
     {
         auto &j = active[s];
         ex->release(s, *j);
-        admitted_bytes -= j->footprint;
+        set_charge(s, ex->retained(s));
         j->slot = -1;
         active[s].reset();
+    }
+
+    int64_t busy_charge(int s, const Job &j) const { return std::max(j.footprint, charge[s] + j.mesh_bytes); }
+
+    // Whether job j fits into idle slot s; under budget pressure the idle
+    // slots' kept scratch is freed first (a device-wide wait, rare).
+    bool fits(int s, const Job &j)
+    {
+        auto need = [&] { return admitted_bytes - charge[s] + busy_charge(s, j); };
+        if (need() <= (int64_t)cfg.hbm_budget_bytes) return true;
+        for (int t = 0; t < (int)active.size(); ++t)
+            if (!active[t] && charge[t] > 0) {
+                ex->trim(t);
+                set_charge(t, ex->retained(t));
+            }
+        return need() <= (int64_t)cfg.hbm_budget_bytes;
     }
 
     // One scheduler pass under the lock; returns true if anything changed.
@@ -375,13 +493,13 @@ struct hsd_server {
         for (int s = 0; s < (int)active.size() && !queue.empty(); ++s) {
             if (active[s]) continue;
             auto j = queue.front();
-            if (admitted_bytes + j->footprint > (int64_t)cfg.hbm_budget_bytes) break;
+            if (!fits(s, *j)) break;
             queue.pop_front();
             j->slot = s;
             j->times.admitted_s = now_s();
             j->times.footprint = j->footprint;
             active[s] = j;
-            admitted_bytes += j->footprint;
+            set_charge(s, busy_charge(s, *j));
             const hsd_status st = ex->start(s, *j);
             if (st != HSD_OK) {
                 complete(j, st);
@@ -465,6 +583,7 @@ static hsd_status server_make(hsd_ctx *ctx, const hsd_server_cfg *cfg, std::uniq
     s->cfg = *cfg;
     s->ex = std::move(ex);
     s->active.assign((size_t)s->ex->slots(), nullptr);
+    s->charge.assign((size_t)s->ex->slots(), 0);
     s->th = std::thread([s] { s->run(); });
     *out = s;
     return HSD_OK;
@@ -488,11 +607,13 @@ hsd_status hsd_server_create(hsd_ctx *ctx, const hsd_server_cfg *cfg, hsd_server
     hsd_status st;
     if ((st = cfg_check(cfg)) != HSD_OK) return st;
     HSD_HIP_TRY(hipSetDevice(ctx->device));
-    ctx_retain(ctx);
     std::unique_ptr<Executor> ex(new DeviceExecutor(ctx, cfg->slots, cfg->chunk_pairs));
+    if ((st = ex->init()) != HSD_OK) return st;   // the executor's destructor frees what was created
+    ctx_retain(ctx);
     return server_make(ctx, cfg, std::move(ex), out);
 }
 
+#ifdef HSD_TEST_HOOKS
 // Test hook (not in the public header): a server whose executor simulates
 // work on the CPU at `pairs_per_s` (each request counts nt x 1000 pairs).
 hsd_status hsd__server_create_fake(const hsd_server_cfg *cfg, double pairs_per_s, hsd_server **out)
@@ -502,6 +623,7 @@ hsd_status hsd__server_create_fake(const hsd_server_cfg *cfg, double pairs_per_s
     std::unique_ptr<Executor> ex(new FakeExecutor(cfg->slots, pairs_per_s, cfg->chunk_pairs));
     return server_make(nullptr, cfg, std::move(ex), out);
 }
+#endif // HSD_TEST_HOOKS
 
 hsd_status hsd_submit(hsd_server *s, const hsd_request *req, uint64_t *ticket)
 {

@@ -1,10 +1,13 @@
 """Replay a request trace against the serving loop and summarise it.
 
 Requests are submitted at their arrival times (a Poisson process in the
-traces of hsd_inputs.serving_trace); latency is measured on the server's
-clock from submit to result.  Reported: p50/p99 latency, distances per
-second over the busy span, the offered load (sum of the requests' measured
-service times over the arrival span) and a per-rule breakdown.
+traces of hsd_inputs.serving_trace; time_scale 0 submits them all at once,
+which saturates the server); latency is measured on the server's clock from
+submit to result.  Reported: p50/p99 latency, completed distances per second
+over the span from the first arrival to the last result, the fraction of
+that span during which the device had at least one request admitted, the
+offered load (the trace's work per second of arrivals over the server's
+measured capacity, when that capacity is given) and a per-rule breakdown.
 """
 from __future__ import annotations
 
@@ -15,8 +18,19 @@ import numpy as np
 from .api import Params, Rule, Server
 
 
+def _busy_fraction(intervals, t0: float, t1: float) -> float:
+    """Length of the union of [a, b) intervals within [t0, t1), over t1 - t0."""
+    busy, end = 0.0, t0
+    for a, b in sorted(intervals):
+        a, b = max(a, end), min(b, t1)
+        if b > a:
+            busy += b - a
+            end = b
+    return busy / max(t1 - t0, 1e-12)
+
+
 def replay(server: Server, trace, rules: dict[str, Rule], params: Params,
-           time_scale: float = 1.0) -> dict:
+           time_scale: float = 1.0, capacity_pairs_per_s: float | None = None) -> dict:
     t_start = time.perf_counter()
     tickets = []
     for req in trace:
@@ -36,22 +50,29 @@ def replay(server: Server, trace, rules: dict[str, Rule], params: Params,
     lat = np.array([t.latency_s for _, t in out])
     ok = np.array([t.status == 0 for _, t in out])
     first = min(t.arrival_s for _, t in out)
+    last_arrival = max(t.arrival_s for _, t in out)
     last = max(t.finished_s for _, t in out)
+    pairs = float(sum(t.result.pairs for _, t in out))
     per_rule = {}
     for name in sorted(set(r.rule for r, _ in out)):
         ls = np.array([t.latency_s for r, t in out if r.rule == name])
         per_rule[name] = {"requests": int(len(ls)), "p50_ms": float(np.percentile(ls, 50) * 1e3),
                           "p99_ms": float(np.percentile(ls, 99) * 1e3)}
-    return {
+    res = {
         "requests": len(out),
         "failed": int((~ok).sum()),
         "p50_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "mean_ms": float(lat.mean() * 1e3),
-        "distances_per_s": len(out) / (last - first),
+        "distances_per_s": float(ok.sum()) / (last - first),
+        "pairs_per_s": pairs / (last - first),
         "span_s": last - first,
         "wall_s": wall,
-        "pairs": float(sum(t.result.pairs for _, t in out)),
+        "pairs": pairs,
+        "device_busy_frac": _busy_fraction([(t.admitted_s, t.finished_s) for _, t in out], first, last),
         "per_rule": per_rule,
         "results": {r.index: t.result.d2 for r, t in out},
     }
+    if capacity_pairs_per_s and last_arrival > first:
+        res["offered_load"] = pairs / (last_arrival - first) / capacity_pairs_per_s
+    return res

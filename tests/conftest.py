@@ -32,5 +32,21 @@ def hsd_ctx():
     ctx.close()
 
 
+@pytest.fixture(scope="session")
+def hooks_ctx():
+    """(library, context handle) of the test-hooks build of the library, for
+    the GPU tests that call its hooks (skips when no GPU is visible)."""
+    import ctypes
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_06340_amd import _lib
+    L = _lib.load_test_hooks()
+    h = ctypes.c_void_p()
+    assert L.hsd_init(0, 0, ctypes.byref(h)) == 0, L.hsd_last_error()
+    yield L, h
+    L.hsd_finalize(h)
+
+
 def golden_path(name):
     return os.path.join(ROOT, "tests", "golden", name)

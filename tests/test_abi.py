@@ -33,6 +33,16 @@ def test_library_exports_every_declared_symbol():
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libhsd.so not built")
+def test_product_library_exports_only_the_header():
+    """The C functions libhsd.so exports are exactly those include/hsd.h
+    declares; the test hooks live in libhsd_testhooks.so only."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = sorted({ln.split()[-1] for ln in out.splitlines() if " T hsd" in ln})
+    assert exported == declared_functions()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhsd.so not built")
 def test_binding_covers_the_header():
     from paper_2304_06340_amd import _lib
     assert set(declared_functions()) == set(_lib.exported_symbols())

@@ -16,14 +16,14 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("n", [8, 12, 24, 27, 48, 64, 81, 96, 192, 243])
-def test_fft3d_against_numpy(hsd_ctx, n):
-    L = hsd_ctx._lib
+def test_fft3d_against_numpy(hooks_ctx, n):
+    L, ctx = hooks_ctx
     f = L.hsd__test_fft3d
     f.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int]
     rng = np.random.default_rng(n)
     x = rng.normal(size=(n, n, n)) + 1j * rng.normal(size=(n, n, n))
     buf = np.ascontiguousarray(np.stack([x.real, x.imag], axis=-1))
-    assert f(hsd_ctx.handle, buf.ctypes.data_as(C.POINTER(C.c_double)), n) == 0
+    assert f(ctx, buf.ctypes.data_as(C.POINTER(C.c_double)), n) == 0
     got = buf[..., 0] + 1j * buf[..., 1]
     ref = np.fft.fftn(x)
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
@@ -31,13 +31,13 @@ def test_fft3d_against_numpy(hsd_ctx, n):
 
 
 @pytest.mark.parametrize("n,e_in,e_out", [(48, 10, 0), (81, 20, 30), (64, 31, 12), (54, 0, 9)])
-def test_fft3d_pruned_against_numpy(hsd_ctx, n, e_in, e_out):
+def test_fft3d_pruned_against_numpy(hooks_ctx, n, e_in, e_out):
     """The pruned passes: input zero outside indices m < e_in or m >= n - e_in
     of every axis (a zero-padded centred grid in wrapped order), outputs
     wanted only where x, y and z lie in the band of half-extent e_out; those
     outputs equal the full transform's.  The values outside the input band
     are set to NaN on the device side's copy: the passes must not read them."""
-    L = hsd_ctx._lib
+    L, ctx = hooks_ctx
     f = L.hsd__test_fft3d_pruned
     f.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_int, C.c_int, C.c_int]
 
@@ -57,7 +57,7 @@ def test_fft3d_pruned_against_numpy(hsd_ctx, n, e_in, e_out):
     buf = np.ascontiguousarray(np.stack([x.real, x.imag], axis=-1))
     inside = occ[:, None, None] & occ[None, :, None] & occ[None, None, :]
     buf[~inside] = np.nan
-    assert f(hsd_ctx.handle, buf.ctypes.data_as(C.POINTER(C.c_double)), n, e_in, e_out) == 0
+    assert f(ctx, buf.ctypes.data_as(C.POINTER(C.c_double)), n, e_in, e_out) == 0
     got = buf[..., 0] + 1j * buf[..., 1]
     ref = np.fft.fftn(x)
     want = band(e_out)

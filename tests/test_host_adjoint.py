@@ -7,8 +7,8 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-LIB = os.path.join(ROOT, "paper_2304_06340_amd", "libhsd.so")
-pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhsd.so not built")
+LIB = os.path.join(ROOT, "paper_2304_06340_amd", "libhsd_testhooks.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhsd_testhooks.so not built")
 dp = C.POINTER(C.c_double)
 
 

@@ -16,8 +16,8 @@ import pytest
 from hsd_inputs import icosphere, perturb_radial, random_rotation, rotate, random_triangles
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-LIB = os.path.join(ROOT, "paper_2304_06340_amd", "libhsd.so")
-pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhsd.so not built")
+LIB = os.path.join(ROOT, "paper_2304_06340_amd", "libhsd_testhooks.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhsd_testhooks.so not built")
 
 dp = C.POINTER(C.c_double)
 

@@ -13,7 +13,7 @@ from scipy import special
 from hsd_inputs import icosphere, random_rotation, rotate, ellipsoid_mesh, torus_mesh
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-LIB = os.path.join(ROOT, "paper_2304_06340_amd", "libhsd.so")
+LIB = os.path.join(ROOT, "paper_2304_06340_amd", "libhsd_testhooks.so")
 
 
 def test_sphere_quadrature_matches_closed_form(orc):
@@ -82,7 +82,7 @@ class _SurfaceDesc(C.Structure):
                 ("b", C.c_double), ("c", C.c_double), ("center", C.c_double * 3), ("reserved", C.c_int32 * 4)]
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="libhsd.so not built")
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libhsd_testhooks.so not built")
 @pytest.mark.parametrize("kind,args", [(0, (1.2, 0.8, 0.6)), (1, (2.0, 0.5, 0.0))])
 def test_library_surface_quadrature_matches_oracle(orc, kind, args):
     """The library's C++ quadrature of its built-in surfaces (host test hook)
