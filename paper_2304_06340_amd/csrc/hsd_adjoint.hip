@@ -28,6 +28,9 @@
 namespace hsd {
 
 constexpr int kAdjNV = 10;   // S_E, V_0[3], V_1[3], V_2[3]
+// Gaps are floored here (per unit radius, or per pair) so that a zero gap
+// needs no special case; r times the floor stays a normal number.
+constexpr double kAdjGapFloor = 1e-150;
 
 // Maclaurin coefficients of the two derivatives:
 //   d/dx sin(x)/x       = sum_{k>=1} (-1)^k     2k     x^(2k-1) / (2k+1)!
@@ -36,11 +39,14 @@ constexpr double dsinc_coef(int k) { return ((k & 1) ? -1.0 : 1.0) * 2.0 * k * i
 constexpr double dcosc_coef(int k) { return ((k & 1) ? 1.0 : -1.0) * (2.0 * k - 1.0) * inv_factorial(2 * k); }
 
 // d/dx sin(x)/x and d/dx (1-cos x)/x (x >= 0, ix = 1/x), with the series
-// (k <= 7, first omitted terms below 1e-16 relative to the leading x/3 and
-// 1/2) below 0.5.
+// (k <= 7, first omitted terms far below 1e-16 relative to the leading x/3
+// and 1/2) below 0.05.  Above it the closed forms (cos x - sinc x)/x and
+// (sin x - (1-cos x)/x)/x lose at most about 6 eps / x^2 to cancellation
+// (2.7e-13 relative at x = 0.05); a lower threshold makes the lanes of a
+// wave (different triangles) take the series less often.
 HSD_HD void dsinc_dcosc(double x, double ix, double sx, double cx, double &dsinc, double &dcosc)
 {
-    if (x < 0.5) {
+    if (x < 0.05) {
         const double x2 = x * x;
         double ps = dsinc_coef(7), pc = dcosc_coef(7);
 #pragma unroll
@@ -87,26 +93,25 @@ HSD_HD void dd2_series_grad(double a, double b, double F[2], double Fa[2], doubl
     Fb[0] = br; Fb[1] = bi;
 }
 
-// One (triangle, node) pair from its phases: hu = exp(-i a/2), hv =
-// exp(-i b/2), e1 = exp(-i theta_mid) as (cos, sin) pairs; ia, ib, iG are
-// 1/a, 1/b, 1/(a+b) (used only where a, b > 0 and G >= tau).  Gives
-// E = exp(-i theta_mid) F and the derivatives D_lo, D_mid, D_hi (complex, in
-// the sorted frame).
-HSD_HD void pair_grad_ph(double a, double b, double tau, cs64 hu, cs64 hv, cs64 e1, double ia, double ib,
-                         double iG, double E[2], double Dlo[2], double Dmid[2], double Dhi[2])
+// The sorted-frame factors of one (triangle, node) pair from its half-gap
+// phases hu = exp(-i a/2), hv = exp(-i b/2): F(a, b) and its derivatives
+// F_a, F_b (complex); ia, ib, iG are 1/a, 1/b, 1/(a+b) (used only where
+// a, b > 0 and G >= tau).
+HSD_HD void pair_factors(double a, double b, double tau, cs64 hu, cs64 hv, double ia, double ib, double iG,
+                         double F[2], double Fa[2], double Fb[2])
 {
-    double F[2], Fa[2], Fb[2];
     const double G = a + b;
     if (G < tau) {
         dd2_series_grad(a, b, F, Fa, Fb);
     } else {
         const double sa = 2.0 * hu.s * hu.c, ca = hu.c * hu.c - hu.s * hu.s;
         const double sb = 2.0 * hv.s * hv.c, cb = hv.c * hv.c - hv.s * hv.s;
-        // sinc and (1-cos)/x of a, b (limits at 0)
-        const double sinc_a = a > 0.0 ? sa * ia : 1.0;
-        const double sinc_b = b > 0.0 ? sb * ib : 1.0;
-        const double cosc_a = a > 0.0 ? 2.0 * hu.s * hu.s * ia : 0.0;
-        const double cosc_b = b > 0.0 ? 2.0 * hv.s * hv.s * ib : 0.0;
+        // sinc and (1-cos)/x of a, b (both gaps floored at kAdjGapFloor, so
+        // that a zero gap gives its limits 1 and 0 without a select)
+        const double sinc_a = sa * ia;
+        const double sinc_b = sb * ib;
+        const double cosc_a = 2.0 * hu.s * hu.s * ia;
+        const double cosc_b = 2.0 * hv.s * hv.s * ib;
         double dsa, dca, dsb, dcb;
         dsinc_dcosc(a, ia, sa, ca, dsa, dca);
         dsinc_dcosc(b, ib, sb, cb, dsb, dcb);
@@ -117,6 +122,15 @@ HSD_HD void pair_grad_ph(double a, double b, double tau, cs64 hu, cs64 hv, cs64 
         Fb[0] = (dcb - F[0]) * iG;
         Fb[1] = (dsb - F[1]) * iG;
     }
+}
+
+// E = exp(-i theta_mid) F and the derivatives D_lo, D_mid, D_hi (complex,
+// in the sorted frame) of one pair; e1 = exp(-i theta_mid) as (cos, sin).
+HSD_HD void pair_grad_ph(double a, double b, double tau, cs64 hu, cs64 hv, cs64 e1, double ia, double ib,
+                         double iG, double E[2], double Dlo[2], double Dmid[2], double Dhi[2])
+{
+    double F[2], Fa[2], Fb[2];
+    pair_factors(a, b, tau, hu, hv, ia, ib, iG, F, Fa, Fb);
     const double er = e1.c, ei = -e1.s;   // exp(-i theta) = (c, -s)
     E[0] = er * F[0] - ei * F[1];
     E[1] = er * F[1] + ei * F[0];
@@ -129,12 +143,34 @@ HSD_HD void pair_grad_ph(double a, double b, double tau, cs64 hu, cs64 hv, cs64 
     Dmid[1] = -E[0] - Dlo[1] - Dhi[1];
 }
 
+// Accumulate one pair into a direction's four sums from the weighted
+// residual q = 2 W conj(R) and the pair's factors: with Q = q exp(-i theta),
+//   S_E  += Re(q E)        = Re(Q F)
+//   S_I  += r Im(q E)      = r Im(Q F)
+//   u_lo += r Re(q D_lo)   = -r Re(Q F_a)
+//   u_hi += r Re(q D_hi)   =  r Re(Q F_b)
+// and u_mid = S_I - u_lo - u_hi once per direction (translation: the three
+// derivatives sum to -i E), so E and the D_j are never formed.
+HSD_HD void pair_accumulate(double qr, double qi, cs64 e1, double r, const double F[2], const double Fa[2],
+                            const double Fb[2], double &sE, double &sI, double &ulo, double &uhi)
+{
+    // exp(-i theta) = (c, -s):  Q = (qr c + qi s) + i (qi c - qr s)
+    const double Qr = __builtin_fma(qr, e1.c, qi * e1.s);
+    const double Qi = __builtin_fma(qi, e1.c, -qr * e1.s);
+    sE = __builtin_fma(Qr, F[0], __builtin_fma(-Qi, F[1], sE));
+    const double rQr = r * Qr, rQi = r * Qi;
+    sI = __builtin_fma(rQr, F[1], __builtin_fma(rQi, F[0], sI));
+    ulo = __builtin_fma(-rQr, Fa[0], __builtin_fma(rQi, Fa[1], ulo));
+    uhi = __builtin_fma(rQr, Fb[0], __builtin_fma(-rQi, Fb[1], uhi));
+}
+
 HSD_HD void pair_grad(double thmid, double a, double b, double tau, double E[2], double Dlo[2],
                       double Dmid[2], double Dhi[2])
 {
-    const double G = a + b;
-    pair_grad_ph(a, b, tau, sincos64(0.5 * a), sincos64(0.5 * b), sincos64(thmid), a > 0.0 ? 1.0 / a : 0.0,
-                 b > 0.0 ? 1.0 / b : 0.0, G > 0.0 ? 1.0 / G : 0.0, E, Dlo, Dmid, Dhi);
+    a = fmax(a, kAdjGapFloor);
+    b = fmax(b, kAdjGapFloor);
+    pair_grad_ph(a, b, tau, sincos64(0.5 * a), sincos64(0.5 * b), sincos64(thmid), 1.0 / a, 1.0 / b, 1.0 / (a + b), E,
+                 Dlo, Dmid, Dhi);
 }
 
 // Per-direction scatter of the three sorted-frame sums to the vertex slots.
@@ -180,9 +216,8 @@ HSD_HD void adjoint_lane_sp(const TriRec &T, const double *dirs, const double *i
         if (v1 < v0) { double t = v0; v0 = v1; v1 = t; int ti = i0; i0 = i1; i1 = ti; }
         if (v2 < v1) { double t = v1; v1 = v2; v2 = t; int ti = i1; i1 = i2; i2 = ti; }
         if (v1 < v0) { double t = v0; v0 = v1; v1 = t; int ti = i0; i0 = i1; i1 = ti; }
-        const double al = v1 - v0, be = v2 - v1, tmid = t0 + v1;
-        const double ial = al > 0.0 ? 1.0 / al : 0.0, ibe = be > 0.0 ? 1.0 / be : 0.0;
-        const double iGc = al + be > 0.0 ? 1.0 / (al + be) : 0.0;
+        const double al = fmax(v1 - v0, kAdjGapFloor), be = fmax(v2 - v1, kAdjGapFloor), tmid = t0 + v1;
+        const double ial = 1.0 / al, ibe = 1.0 / be, iGc = 1.0 / (al + be);
         const double wd = wdir[d];
         const double fr[3] = {tmid, 0.5 * al, 0.5 * be};
         cs64 step[3], c0[3];
@@ -191,7 +226,7 @@ HSD_HD void adjoint_lane_sp(const TriRec &T, const double *dirs, const double *i
             c0[c] = sincos64(h * fr[c]);
             step[c] = pmul(c0[c], c0[c]);
         }
-        double sE = 0.0, ulo = 0.0, umid = 0.0, uhi = 0.0;
+        double sE = 0.0, sI = 0.0, ulo = 0.0, uhi = 0.0;
         for (int k = 0; k < nh; ++k) {
             const double hx = hx_tab[k];
             cs64 bk[3];
@@ -217,20 +252,16 @@ HSD_HD void adjoint_lane_sp(const TriRec &T, const double *dirs, const double *i
                     const double W = wd * wtab[ir];
                     const double2 R = resid[node];
                     const double qr = 2.0 * W * R.x, qi = -2.0 * W * R.y;
-                    double E[2], Dlo[2], Dmid[2], Dhi[2];
-                    pair_grad_ph(r * al, r * be, tau, ph[1], ph[2], ph[0], irr * ial, irr * ibe, irr * iGc, E, Dlo,
-                                 Dmid, Dhi);
-                    sE += qr * E[0] - qi * E[1];
-                    ulo += r * (qr * Dlo[0] - qi * Dlo[1]);
-                    umid += r * (qr * Dmid[0] - qi * Dmid[1]);
-                    uhi += r * (qr * Dhi[0] - qi * Dhi[1]);
+                    double F[2], Fa[2], Fb[2];
+                    pair_factors(r * al, r * be, tau, ph[1], ph[2], irr * ial, irr * ibe, irr * iGc, F, Fa, Fb);
+                    pair_accumulate(qr, qi, ph[0], r, F, Fa, Fb, sE, sI, ulo, uhi);
                 }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) cp[c] = pmul(cp[c], step[c]);
             }
         }
         acc[0] += sE;
-        const double u[3] = {ulo, umid, uhi};
+        const double u[3] = {ulo, sI - ulo - uhi, uhi};
         const int idx[3] = {i0, i1, i2};
         adjoint_scatter(nx, ny, nz, u, idx, acc);
     }
@@ -254,24 +285,22 @@ HSD_HD void adjoint_lane(const TriRec &T, const double *dirs, const double *radi
         if (v1 < v0) { double t = v0; v0 = v1; v1 = t; int ti = i0; i0 = i1; i1 = ti; }
         if (v2 < v1) { double t = v1; v1 = v2; v2 = t; int ti = i1; i1 = i2; i2 = ti; }
         if (v1 < v0) { double t = v0; v0 = v1; v1 = t; int ti = i0; i0 = i1; i1 = ti; }
-        const double al = v1 - v0, be = v2 - v1, tmid = t0 + v1;
+        const double al = fmax(v1 - v0, kAdjGapFloor), be = fmax(v2 - v1, kAdjGapFloor), tmid = t0 + v1;
         const double wd = wdir ? wdir[d] : 1.0;
-        double sE = 0.0, ulo = 0.0, umid = 0.0, uhi = 0.0;
+        double sE = 0.0, sI = 0.0, ulo = 0.0, uhi = 0.0;
         for (int ir = 0; ir < n_rad; ++ir) {
             const double r = radii[ir];
             const int64_t node = d * n_rad + ir;
             const double W = wd * wtab[wdir ? ir : node];
             const double2 R = resid[node];
             const double qr = 2.0 * W * R.x, qi = -2.0 * W * R.y;   // q = 2 W conj(R)
-            double E[2], Dlo[2], Dmid[2], Dhi[2];
-            pair_grad(r * tmid, r * al, r * be, tau, E, Dlo, Dmid, Dhi);
-            sE += qr * E[0] - qi * E[1];
-            ulo += r * (qr * Dlo[0] - qi * Dlo[1]);
-            umid += r * (qr * Dmid[0] - qi * Dmid[1]);
-            uhi += r * (qr * Dhi[0] - qi * Dhi[1]);
+            const double a = r * al, b = r * be, G = a + b;
+            double F[2], Fa[2], Fb[2];
+            pair_factors(a, b, tau, sincos64(0.5 * a), sincos64(0.5 * b), 1.0 / a, 1.0 / b, 1.0 / G, F, Fa, Fb);
+            pair_accumulate(qr, qi, sincos64(r * tmid), r, F, Fa, Fb, sE, sI, ulo, uhi);
         }
         acc[0] += sE;
-        const double u[3] = {ulo, umid, uhi};
+        const double u[3] = {ulo, sI - ulo - uhi, uhi};
         const int idx[3] = {i0, i1, i2};
         adjoint_scatter(nx, ny, nz, u, idx, acc);
     }

@@ -153,7 +153,7 @@ HSD_HD cs64 group_first_phase(cs64 own, double hc, const cs64 *turn)
 // centre phases of the two half gaps are stored times sqrt(K_a), sqrt(K_b),
 // so the consumer's phase products give sqrt(K) e^{-i r g/2} and the four
 // terms are two squares and two products of their parts.  The sign of J
-// (-1 for a second mesh) rides on the theta_mid phase row, the series
+// (-1 for a second mesh) rides on the theta_mid half-node phase, the series
 // coefficients carry |J|.
 template <int PG, bool ONE>
 HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
@@ -182,10 +182,9 @@ HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, i
     const double rab = rcp64(td.ac * td.bc);
     const double t = 2.0 * aJ * td.iG;
     const double ska = __builtin_sqrt(t * (td.bc * rab)), skb = __builtin_sqrt(t * (td.ac * rab));
-    const double sgn = td.J < 0.0 ? -1.0 : 1.0;
+    if (td.J < 0.0) Bk[0] = cs64{-Bk[0].c, -Bk[0].s};
 #pragma unroll
     for (int q = 0; q < PG; ++q) {
-        Cp[q][0] = cs64{sgn * Cp[q][0].c, sgn * Cp[q][0].s};
         Cp[q][1] = cs64{ska * Cp[q][1].c, ska * Cp[q][1].s};
         Cp[q][2] = cs64{skb * Cp[q][2].c, skb * Cp[q][2].s};
     }
