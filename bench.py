@@ -106,6 +106,65 @@ def flops_per_pair(spec, form="fp64") -> float:
     return 32.0 + (producer + 46.0 / 8) / (16 * PG) + 1.0 / 16
 
 
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+
+
+def _nufft_roofline(ctx, mesh, rule, params) -> dict:
+    """Per-stage device times of one NUFFT distance (HIP events at the stage
+    boundaries, on the library's stream) with each stage's algorithmic bytes
+    (the library's count of what the stage must read and write), and the
+    HBM roofline of the FFT passes (the stage whose design is HBM-bound) and
+    of the whole pipeline."""
+    import paper_2304_06340_amd as hsd
+    ctx.set_stage_timing(True)
+    hsd.distance(ctx, mesh, None, rule, params)
+    st = ctx.nufft_stage_stats()
+    ctx.set_stage_timing(False)
+    stages = {k: {"ms": ms, "bytes": b, "GB_per_s": b / (ms * 1e-3) / 1e9 if ms > 0 else None}
+              for k, (ms, b) in st.items()}
+    fft_ms, fft_b = st["fft"]
+    tot_ms = sum(ms for ms, _ in st.values())
+    tot_b = sum(b for _, b in st.values())
+    ach = fft_b / (fft_ms * 1e-3) / 1e9
+    return {"roofline": {"bound": "hbm", "kernel": "k_fft_axis (three pruned passes)", "achieved": ach,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                         "traffic": None, "kernel_ms": fft_ms, "algorithmic_bytes": fft_b,
+                         "pipeline_GB_per_s": tot_b / (tot_ms * 1e-3) / 1e9,
+                         "pipeline_frac": tot_b / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "stages": stages}
+
+
+def _cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_full_runs() -> list:
+    """Complete oracle d2 evaluations stored with the parity fixtures (wall
+    seconds on the machine that wrote them, named in each entry): level 2
+    and level 7 on the 262,144-node rule, levels 3-5 on the 8,388,608-node
+    rule."""
+    import json
+    runs = []
+    for name, nodes in (("small_rule_levels.json", 262144), ("large_rule_levels.json", 8388608)):
+        path = os.path.join(ROOT, "tests", "golden", name)
+        if not os.path.exists(path):
+            continue
+        g = json.load(open(path))
+        host = g.get("host", {})
+        for L, sec in sorted(g.get("seconds", {}).items(), key=lambda kv: int(kv[0])):
+            pairs = 20.0 * 4 ** int(L) * nodes
+            runs.append({"level": int(L), "nodes": nodes, "pairs": pairs, "seconds": sec,
+                         "pairs_per_s": pairs / sec, "host": host.get("cpu", "unknown"),
+                         "threads": host.get("threads")})
+    return runs
+
+
 def _progress(msg: str) -> None:
     """One line per finished section on stderr (stdout carries only the JSON line)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -226,7 +285,8 @@ def main():
         _progress(f"nufft {walln * 1e3:.1f} ms per distance")
         out["nufft"] = {"ms_per_step": walln * 1e3, "distances_per_s": 1.0 / walln,
                         "points": resn[-1].pairs, "rel_err_vs_fp64_direct": abs(resn[-1].d2 - d2_64) / d2_64,
-                        "note": "error vs the exact-triangle d2 includes the 7-point rule's model error"}
+                        "note": "error vs the exact-triangle d2 includes the 7-point rule's model error",
+                        **_nufft_roofline(ctx, mesh, rule, pn)}
     if not args.no_paper:
         # The paper's own configuration (section 4, Figs. 3(b) and 4): level 7,
         # exp(-2 pi i eta.x) convention with order -10, trapezoid rule on
@@ -249,6 +309,7 @@ def main():
                         "GL 8x8 points (20,971,520), NUFFT tol 1e-7 (type 1 on the lattice)",
             "ms_per_distance": wp * 1e3, "transform_ms": resp[-1].transform_ms,
             "relative_H-10_error": math.sqrt(resp[-1].d2 / norm2),
+            **_nufft_roofline(ctx, mesh, cube, pp),
             "paper_reference": "0.94 s on an RTX A6000 for the same N, M, xi_max and point rule "
                                "(context: other hardware, allocation and reductions excluded there)"}
         empty.close()
@@ -332,10 +393,13 @@ def main():
         oracle.transform(v, f, orule.nodes[idx])
         dt = time.perf_counter() - t0
         _progress(f"cpu oracle {dt:.1f} s")
-        out["cpu_baseline"] = {"value": len(idx) * len(f) / dt, "unit": "pairs/s",
-                               "cores": oracle.num_threads(), "kind": "oracle",
+        cores = oracle.num_threads()
+        rate = len(idx) * len(f) / dt
+        out["cpu_baseline"] = {"value": rate, "unit": "pairs/s", "cores": cores, "kind": "oracle",
+                               "per_core": rate / cores, "cpu": _cpu_model(),
                                "sample": f"oracle.transform of the same mesh at {len(idx)} seeded "
-                                         f"rule nodes ({len(idx) * len(f):.3e} pairs, {dt:.1f} s)"}
+                                         f"rule nodes ({len(idx) * len(f):.3e} pairs, {dt:.1f} s)",
+                               "full_runs": _oracle_full_runs()}
     print(json.dumps(out), flush=True)
     mesh.close()
     rule.close()

@@ -159,6 +159,18 @@ hsd_status hsd_ctx_set_stream(hsd_ctx *ctx, void *hip_stream);
 /* Bytes of device memory currently allocated by the context. */
 size_t hsd_ctx_bytes_in_use(const hsd_ctx *ctx);
 
+/* Stage timing of the NUFFT path (diagnostics).  With enable != 0 the
+ * context's later NUFFT3 transforms (hsd_distance, hsd_transform_rule)
+ * record HIP events at their stage boundaries on the context's stream.
+ * hsd_nufft_stage_stats then gives, for the last such transform, ms[5] the
+ * device time and bytes[5] the algorithmic HBM bytes (what each stage must
+ * read and write at least) of the stages 0 points, sort and bins, 1 spread,
+ * 2 pre-deconvolution, 3 the three FFT passes, 4 read-out (interpolation at
+ * the nodes, or the lattice gather of type 1); it waits for the last event.
+ * Errors: EINVAL (NULL, or no timed transform yet), EDEVICE. */
+hsd_status hsd_ctx_set_stage_timing(hsd_ctx *ctx, int32_t enable);
+hsd_status hsd_nufft_stage_stats(hsd_ctx *ctx, double *ms, double *bytes);
+
 /* Destroy the context and everything it still owns. */
 void hsd_finalize(hsd_ctx *ctx);
 

@@ -90,6 +90,8 @@ SIGNATURES = {
     "hsd_rule_destroy": (None, [C.c_void_p]),
     "hsd_distance": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                  C.POINTER(Params), C.POINTER(Result)]),
+    "hsd_ctx_set_stage_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "hsd_nufft_stage_stats": (C.c_int32, [C.c_void_p, dp, dp]),
     "hsd_distance_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                          C.POINTER(Params), C.POINTER(Result)]),
     "hsd_distance_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

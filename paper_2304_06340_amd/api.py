@@ -112,6 +112,18 @@ class Context:
     def bytes_in_use(self) -> int:
         return int(self._lib.hsd_ctx_bytes_in_use(self.handle))
 
+    def set_stage_timing(self, enable: bool = True) -> None:
+        """Record the NUFFT path's stage times (hsd_ctx_set_stage_timing)."""
+        _check(self._lib.hsd_ctx_set_stage_timing(self.handle, 1 if enable else 0))
+
+    def nufft_stage_stats(self) -> dict:
+        """{stage: (ms, algorithmic bytes)} of the last timed NUFFT transform."""
+        ms = (C.c_double * 5)()
+        by = (C.c_double * 5)()
+        _check(self._lib.hsd_nufft_stage_stats(self.handle, ms, by))
+        names = ("points_sort", "spread", "predeconv", "fft", "readout")
+        return {n: (ms[i], by[i]) for i, n in enumerate(names)}
+
     def close(self) -> None:
         if self.handle:
             self._lib.hsd_finalize(self.handle)

@@ -433,6 +433,29 @@ hsd_status hsd_ctx_set_stream(hsd_ctx *ctx, void *stream)
 
 size_t hsd_ctx_bytes_in_use(const hsd_ctx *ctx) { return ctx ? ctx->in_use.load() : 0; }
 
+hsd_status hsd_ctx_set_stage_timing(hsd_ctx *ctx, int32_t enable)
+{
+    if (!ctx) { set_error("context is NULL"); return HSD_EINVAL; }
+    ctx->stage_timing = enable != 0;
+    return HSD_OK;
+}
+
+hsd_status hsd_nufft_stage_stats(hsd_ctx *ctx, double *ms, double *bytes)
+{
+    if (!ctx || !ms || !bytes) { set_error("NULL argument"); return HSD_EINVAL; }
+    NufftScratch &sc = ctx->nufft;
+    if (!sc.timed) { set_error("no timed NUFFT transform on this context"); return HSD_EINVAL; }
+    HSD_HIP_TRY(hipSetDevice(ctx->device));
+    for (int i = 0; i < 5; ++i) {
+        float t = 0.0f;
+        HSD_HIP_TRY(hipEventSynchronize(sc.ev[i + 1]));
+        HSD_HIP_TRY(hipEventElapsedTime(&t, sc.ev[i], sc.ev[i + 1]));
+        ms[i] = (double)t;
+        bytes[i] = sc.stage_bytes[i];
+    }
+    return HSD_OK;
+}
+
 void hsd_finalize(hsd_ctx *ctx)
 {
     if (!ctx) return;

@@ -265,6 +265,14 @@ static int lines_per_block(int n)
     return std::max(1, std::min(kFftMaxElems / n, 16));
 }
 
+double fft3d_bytes(int n, int e_in, int e_out)
+{
+    const double i = (e_in > 0 && 2 * e_in < n) ? 2.0 * e_in : (double)n;
+    const double o = (e_out > 0 && 2 * e_out < n) ? 2.0 * e_out : (double)n;
+    // z: i x i lines, y: i x o lines, x: o x o lines; each reads i, writes o
+    return 16.0 * (i + o) * (i * i + i * o + o * o);
+}
+
 hsd_status fft3d_forward(hipStream_t st, const FftPlan &p, double2 *data, int e_in, int e_out)
 {
     const int n = p.n;

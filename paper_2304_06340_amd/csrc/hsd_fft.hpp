@@ -27,5 +27,9 @@ int fft_next_size(int n);
 //    reach them are skipped, each line is written only in the band, and the
 //    rest of the array is left undefined.
 hsd_status fft3d_forward(hipStream_t st, const FftPlan &p, double2 *data, int e_in = 0, int e_out = 0);
+// Bytes the three passes of fft3d_forward(n, e_in, e_out) read and write:
+// each pass reads its lines in the input band and writes them in the output
+// band, 16 bytes per complex value.
+double fft3d_bytes(int n, int e_in, int e_out);
 
 } // namespace hsd

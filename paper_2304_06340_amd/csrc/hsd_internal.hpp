@@ -84,6 +84,12 @@ struct NufftScratch {
     DevBuf pts, spts, keys, keys2, iota, offs, perm, sorttmp, grid1, fine, tri, ftq, hinv;
     DevBuf titems, tstart, itile, tilebuf, scantmp;   // spread work items per tile
     std::unique_ptr<FftPlan> plan;
+    // stage timing of the last transform (recorded when the context asks):
+    // events at the stage boundaries and each stage's algorithmic bytes
+    hipEvent_t ev[6] = {};
+    bool timed = false;
+    std::vector<double> tabs_on_device;   // contents of tri, ftq, hinv (skip unchanged uploads)
+    double stage_bytes[5] = {};
     NufftScratch();
     ~NufftScratch();
     size_t bytes() const;    // device bytes held
@@ -106,6 +112,7 @@ struct hsd_ctx {
     double *host_result = nullptr;   // pinned 8-byte readback
     std::mutex mu;
     int num_cu = 256;
+    bool stage_timing = false;   // record NUFFT stage events (hsd_ctx_set_stage_timing)
     std::atomic<int> refs{1};
 };
 

@@ -633,7 +633,11 @@ static double es_ft_host(const std::vector<double2> &tab, double k)
 }
 
 NufftScratch::NufftScratch() = default;
-NufftScratch::~NufftScratch() = default;
+NufftScratch::~NufftScratch()
+{
+    for (hipEvent_t &e : ev)
+        if (e) (void)hipEventDestroy(e);
+}
 
 size_t NufftScratch::bytes() const
 {
@@ -647,6 +651,7 @@ size_t NufftScratch::bytes() const
 
 void NufftScratch::release()
 {
+    tabs_on_device.clear();
     for (DevBuf *x : {&pts, &spts, &keys, &keys2, &iota, &offs, &perm, &sorttmp, &grid1, &fine, &tri, &ftq, &hinv,
                       &titems, &tstart, &itile, &tilebuf, &scantmp})
         x->release();
@@ -779,15 +784,30 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
         if (b.ptr && b.bytes >= bytes) return HSD_OK;
         return b.alloc(ctx, std::max<size_t>(bytes, 8));
     };
-    if ((stt = ens(sc.tri, trule.size() * sizeof(double4))) != HSD_OK) return stt;
-    if ((stt = ens(sc.ftq, ftq.size() * sizeof(double2))) != HSD_OK) return stt;
-    if ((stt = ens(sc.hinv, (hinv.size() + dec.size()) * sizeof(double))) != HSD_OK) return stt;
-    HSD_HIP_TRY(hipMemcpyAsync(sc.tri.ptr, trule.data(), trule.size() * sizeof(double4), hipMemcpyHostToDevice, st));
-    HSD_HIP_TRY(hipMemcpyAsync(sc.ftq.ptr, ftq.data(), ftq.size() * sizeof(double2), hipMemcpyHostToDevice, st));
-    HSD_HIP_TRY(hipMemcpyAsync(sc.hinv.ptr, hinv.data(), hinv.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    if (!dec.empty())
-        HSD_HIP_TRY(hipMemcpyAsync(sc.hinv.as<double>() + hinv.size(), dec.data(), dec.size() * sizeof(double),
-                                   hipMemcpyHostToDevice, st));
+    // the small tables (triangle rule, kernel transform, deconvolution) go
+    // to the device only when they differ from the ones already there: a
+    // copy from pageable memory costs the stream tens of microseconds each
+    std::vector<double> tabs;
+    tabs.reserve(trule.size() * 4 + ftq.size() * 2 + hinv.size() + dec.size() + 1);
+    for (const auto &t : trule) tabs.insert(tabs.end(), {t.x, t.y, t.z, t.w});
+    for (const auto &t : ftq) tabs.insert(tabs.end(), {t.x, t.y});
+    tabs.insert(tabs.end(), hinv.begin(), hinv.end());
+    tabs.push_back((double)dec.size());
+    tabs.insert(tabs.end(), dec.begin(), dec.end());
+    if (tabs != sc.tabs_on_device || !sc.tri.ptr) {
+        if ((stt = ens(sc.tri, trule.size() * sizeof(double4))) != HSD_OK) return stt;
+        if ((stt = ens(sc.ftq, ftq.size() * sizeof(double2))) != HSD_OK) return stt;
+        if ((stt = ens(sc.hinv, (hinv.size() + dec.size()) * sizeof(double))) != HSD_OK) return stt;
+        HSD_HIP_TRY(hipMemcpyAsync(sc.tri.ptr, trule.data(), trule.size() * sizeof(double4), hipMemcpyHostToDevice,
+                                   st));
+        HSD_HIP_TRY(hipMemcpyAsync(sc.ftq.ptr, ftq.data(), ftq.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+        HSD_HIP_TRY(hipMemcpyAsync(sc.hinv.ptr, hinv.data(), hinv.size() * sizeof(double), hipMemcpyHostToDevice,
+                                   st));
+        if (!dec.empty())
+            HSD_HIP_TRY(hipMemcpyAsync(sc.hinv.as<double>() + hinv.size(), dec.data(), dec.size() * sizeof(double),
+                                       hipMemcpyHostToDevice, st));
+        sc.tabs_on_device.swap(tabs);
+    }
     if ((stt = ens(sc.pts, (size_t)np * sizeof(double4))) != HSD_OK) return stt;
     if ((stt = ens(sc.spts, (size_t)np * sizeof(double4))) != HSD_OK) return stt;
     if ((stt = ens(sc.keys, (size_t)np * sizeof(int))) != HSD_OK) return stt;
@@ -830,6 +850,17 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     const TriRec *A = mu->tris.as<const TriRec>();
     const TriRec *B = nu ? nu->tris.as<const TriRec>() : nullptr;
     const int64_t nB = nu ? nu->nt : 0;
+    // stage boundaries (events only when the context records stage times):
+    // 0 points, sort and bins | 1 spread | 2 pre-deconvolution | 3 FFT |
+    // 4 read-out
+    sc.timed = ctx->stage_timing;
+    auto mark = [&](int i) -> hsd_status {
+        if (!sc.timed) return HSD_OK;
+        if (!sc.ev[i]) HSD_HIP_TRY(hipEventCreate(&sc.ev[i]));
+        HSD_HIP_TRY(hipEventRecord(sc.ev[i], st));
+        return HSD_OK;
+    };
+    if ((stt = mark(0)) != HSD_OK) return stt;
     if (np > 0) {
         const unsigned g = (unsigned)((np + 255) / 256);
         hipLaunchKernelGGL(k_nufft_points, dim3(g), dim3(256), 0, st, A, mu->nt, B, nB, sc.tri.as<const double4>(), nq,
@@ -855,6 +886,7 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     hipLaunchKernelGGL(k_item_map, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st,
                        sc.tstart.as<const int>(), ntiles, sc.itile.as<int>());
     HSD_HIP_TRY(hipGetLastError());
+    if ((stt = mark(1)) != HSD_OK) return stt;
     hipLaunchKernelGGL(k_spread, dim3((unsigned)max_items), dim3(64), 0, st, sc.spts.as<const double4>(),
                        sc.offs.as<const int>(), sc.tstart.as<const int>(), sc.itile.as<const int>(), nbx, n1, h1,
                        0.5 * w, beta, sc.grid1.as<double>(), sc.tilebuf.as<double>());
@@ -862,6 +894,7 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)ntiles), dim3(64), 0, st, sc.tilebuf.as<const double>(),
                        sc.tstart.as<const int>(), nbx, n1, sc.grid1.as<double>());
     HSD_HIP_TRY(hipGetLastError());
+    if ((stt = mark(2)) != HSD_OK) return stt;
     // the spread grid is zero beyond |l - n1/2| > X / h1 + w / 2 (all points
     // lie within X of the origin), so the fine grid is zero outside the
     // wrapped indices m < e, m >= n2 - e: only that band is written, and the
@@ -877,18 +910,34 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
                            sc.grid1.as<const double>(), n1, sc.hinv.as<const double>(), n2, cnt, e, gap,
                            sc.fine.as<double2>());
         HSD_HIP_TRY(hipGetLastError());
+        sc.stage_bytes[2] = (double)tot * (8.0 + 16.0);
     }
+    if ((stt = mark(3)) != HSD_OK) return stt;
     // and only the indices the read-out touches are wanted: the lattice
     // indices |k| <= M / 2, or the interpolation stencils around the scaled
     // targets |u| <= S n2 h1 / (2 pi) (w points from ceil(u - w/2))
     const int e_want = lattice ? rule->cube_M / 2 + 2
                                : std::min(n2 / 2, (int)std::floor(S * n2 * h1 / (2.0 * kPi) + 0.5 * w) + 2);
     if ((stt = fft3d_forward(st, plan, sc.fine.as<double2>(), e_occ, e_want)) != HSD_OK) return stt;
+    if ((stt = mark(4)) != HSD_OK) return stt;
+    // algorithmic bytes: triangle records read, points and keys written,
+    // sorted (keys and values in and out) and gathered | sorted points read,
+    // spread grid written | (above) | the FFT passes' band reads and writes |
+    // the wanted band read once, one value written per target (plus its
+    // node and deconvolution factor for the ball rules)
+    sc.stage_bytes[0] = (double)(mu->nt + nB) * sizeof(TriRec) + (double)np * (32.0 + 8.0 + 16.0 + 68.0);
+    sc.stage_bytes[1] = (double)np * 32.0 + (double)n1 * n1 * n1 * 8.0;
+    sc.stage_bytes[3] = fft3d_bytes(n2, e_occ, e_want);
+    {
+        const double ew = (e_want > 0 && 2 * e_want < n2) ? 2.0 * e_want : (double)n2;
+        sc.stage_bytes[4] = ew * ew * ew * 16.0 + (double)N * (lattice ? 16.0 + 16.0 : 16.0 + 8.0 + 4.0);
+    }
     if (lattice) {
         hipLaunchKernelGGL(k_lattice_out, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
                            sc.fine.as<const double2>(), n2, rule->d_nodes.as<const double>(), N, 1.0 / rule->cube_h,
                            rule->cube_M, sc.hinv.as<const double>() + hinv.size(), out);
         HSD_HIP_TRY(hipGetLastError());
+        if ((stt = mark(5)) != HSD_OK) return stt;
         if (pairs) *pairs = (double)np;
         return HSD_OK;
     }
@@ -989,6 +1038,7 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
         }
     }
     HSD_HIP_TRY(hipGetLastError());
+    if ((stt = mark(5)) != HSD_OK) return stt;
     if (pairs) *pairs = (double)np;
     return HSD_OK;
 }

@@ -46,10 +46,23 @@ def sampled(name, level, spec, n_samples=4096, seed=7):
     print(f"{name}: {n_samples} nodes x {len(f)} triangles in {dt:.1f}s", flush=True)
 
 
+def _host():
+    model = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu": model, "threads": oracle.num_threads(),
+            "note": "the machine make_golden.py ran on (its oracle timings)"}
+
+
 def d2_levels(name, levels, spec, s=1.0):
     rule = _rule(spec)
     out = {"rule": spec, "s": s, "d2": {}, "seconds": {},
-           "note": "oracle.distance vs the unit sphere; written by make_golden.py"}
+           "note": "oracle.distance vs the unit sphere; written by make_golden.py", "host": _host()}
     path = os.path.join(HERE, name + ".json")
     if os.path.exists(path):
         old = json.load(open(path))

@@ -307,3 +307,25 @@ def test_nufft_full_size_against_stored_point_sum(hsd_ctx, name, tol):
     assert err <= tol + dnode
     mesh.close()
     rule.close()
+
+
+def test_nufft_stage_stats(hsd_ctx):
+    """The stage timing of the NUFFT path: five stages with positive device
+    times that add up to the transform's own time, and algorithmic bytes
+    that include the FFT passes' band traffic."""
+    v, f = icosphere(4)
+    rule = hsd.Rule.spherical_product(hsd_ctx, 64.0, 8, 16, 32, 64)
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    p = hsd.Params(method="nufft3", nufft_tol=1e-9)
+    hsd.distance(hsd_ctx, mesh, None, rule, p)
+    hsd_ctx.set_stage_timing(True)
+    res = hsd.distance(hsd_ctx, mesh, None, rule, p)
+    st = hsd_ctx.nufft_stage_stats()
+    hsd_ctx.set_stage_timing(False)
+    print({k: (round(ms, 3), f"{b:.3e}") for k, (ms, b) in st.items()}, res.transform_ms)
+    assert list(st) == ["points_sort", "spread", "predeconv", "fft", "readout"]
+    assert all(ms >= 0.0 and b > 0.0 for ms, b in st.values())
+    total = sum(ms for ms, _ in st.values())
+    assert 0.8 * res.transform_ms <= total <= 1.05 * res.transform_ms + 0.05
+    mesh.close()
+    rule.close()
