@@ -88,7 +88,8 @@ struct NufftScratch {
     // events at the stage boundaries and each stage's algorithmic bytes
     hipEvent_t ev[6] = {};
     bool timed = false;
-    std::vector<double> tabs_on_device;   // contents of tri, ftq, hinv (skip unchanged uploads)
+    std::vector<double> tab_key;          // parameters of the tables in tri, ftq, hinv
+    int nq = 0, nftq = 0, nhinv = 0;      // their lengths
     double stage_bytes[5] = {};
     NufftScratch();
     ~NufftScratch();

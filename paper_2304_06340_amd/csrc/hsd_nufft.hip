@@ -651,7 +651,7 @@ size_t NufftScratch::bytes() const
 
 void NufftScratch::release()
 {
-    tabs_on_device.clear();
+    tab_key.clear();
     for (DevBuf *x : {&pts, &spts, &keys, &keys2, &iota, &offs, &perm, &sorttmp, &grid1, &fine, &tri, &ftq, &hinv,
                       &titems, &tstart, &itile, &tilebuf, &scantmp})
         x->release();
@@ -752,31 +752,7 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     const double S = std::max(sp ? rule->sp.r_max : rule->extent, 1e-3);   // target extent per axis
     const int nbx = (n1 + kBin - 1) / kBin;
     const int nbins = nbx * nbx * nbx;
-    std::vector<double4> trule;
-    tri_rule_table(p->tri_rule, trule);
-    const int nq = (int)trule.size();
     const int64_t ntri = mu->nt + (nu ? nu->nt : 0);
-    const int64_t np = ntri * nq;
-    // kernel-transform tables
-    std::vector<double2> ftq;
-    es_ft_table(beta, 4 * w + 24, ftq);
-    std::vector<double> hinv(n1, 1.0), dec;
-    if (!lattice) {
-        for (int l = 0; l < n1; ++l) {
-            const int lp = l - n1 / 2;
-            // H^_l = (1/2pi) int h(t) e^{-ilt} dt with h(t) = psi(t n2 / (pi w))
-            const double Hl = (double)w / (2.0 * n2) * es_ft_host(ftq, lp * w * kPi / n2);
-            hinv[l] = 1.0 / Hl;
-        }
-    } else {
-        // spreading with phi(t) = psi(t n / (pi w)) on spacing 2 pi / n gives
-        // sum_l b_l e^{-ik t_l} = (n / 2 pi)^3 prod phi^(k_a) sum_j c_j e^{-ik.t_j},
-        // phi^(k) = (pi w / n) int_{-1}^{1} psi(z) e^{-i k (pi w / n) z} dz
-        const int M = rule->cube_M;
-        dec.resize((size_t)M + 1);
-        for (int k = -M / 2; k <= M / 2; ++k)
-            dec[(size_t)(k + M / 2)] = 2.0 / ((double)w * es_ft_host(ftq, k * kPi * w / n1));
-    }
     const int64_t N = rule->n_nodes;
     // grow-only scratch: a reallocation frees first, and hipFree waits for
     // the whole device (other serving slots included)
@@ -784,17 +760,35 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
         if (b.ptr && b.bytes >= bytes) return HSD_OK;
         return b.alloc(ctx, std::max<size_t>(bytes, 8));
     };
-    // the small tables (triangle rule, kernel transform, deconvolution) go
-    // to the device only when they differ from the ones already there: a
-    // copy from pageable memory costs the stream tens of microseconds each
-    std::vector<double> tabs;
-    tabs.reserve(trule.size() * 4 + ftq.size() * 2 + hinv.size() + dec.size() + 1);
-    for (const auto &t : trule) tabs.insert(tabs.end(), {t.x, t.y, t.z, t.w});
-    for (const auto &t : ftq) tabs.insert(tabs.end(), {t.x, t.y});
-    tabs.insert(tabs.end(), hinv.begin(), hinv.end());
-    tabs.push_back((double)dec.size());
-    tabs.insert(tabs.end(), dec.begin(), dec.end());
-    if (tabs != sc.tabs_on_device || !sc.tri.ptr) {
+    // The small tables (triangle rule, kernel transform, deconvolution)
+    // depend only on these parameters; they are rebuilt on the host and
+    // uploaded only when the parameters change (the host work and the
+    // pageable copies would otherwise hold up the stream on every call).
+    const std::vector<double> key = {(double)p->tri_rule, (double)w, beta, (double)n1, (double)n2,
+                                     lattice ? 1.0 : 0.0, lattice ? (double)rule->cube_M : 0.0};
+    if (key != sc.tab_key || !sc.tri.ptr) {
+        std::vector<double4> trule;
+        tri_rule_table(p->tri_rule, trule);
+        // kernel-transform tables
+        std::vector<double2> ftq;
+        es_ft_table(beta, 4 * w + 24, ftq);
+        std::vector<double> hinv(n1, 1.0), dec;
+        if (!lattice) {
+            for (int l = 0; l < n1; ++l) {
+                const int lp = l - n1 / 2;
+                // H^_l = (1/2pi) int h(t) e^{-ilt} dt with h(t) = psi(t n2 / (pi w))
+                const double Hl = (double)w / (2.0 * n2) * es_ft_host(ftq, lp * w * kPi / n2);
+                hinv[l] = 1.0 / Hl;
+            }
+        } else {
+            // spreading with phi(t) = psi(t n / (pi w)) on spacing 2 pi / n gives
+            // sum_l b_l e^{-ik t_l} = (n / 2 pi)^3 prod phi^(k_a) sum_j c_j e^{-ik.t_j},
+            // phi^(k) = (pi w / n) int_{-1}^{1} psi(z) e^{-i k (pi w / n) z} dz
+            const int M = rule->cube_M;
+            dec.resize((size_t)M + 1);
+            for (int k = -M / 2; k <= M / 2; ++k)
+                dec[(size_t)(k + M / 2)] = 2.0 / ((double)w * es_ft_host(ftq, k * kPi * w / n1));
+        }
         if ((stt = ens(sc.tri, trule.size() * sizeof(double4))) != HSD_OK) return stt;
         if ((stt = ens(sc.ftq, ftq.size() * sizeof(double2))) != HSD_OK) return stt;
         if ((stt = ens(sc.hinv, (hinv.size() + dec.size()) * sizeof(double))) != HSD_OK) return stt;
@@ -806,8 +800,13 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
         if (!dec.empty())
             HSD_HIP_TRY(hipMemcpyAsync(sc.hinv.as<double>() + hinv.size(), dec.data(), dec.size() * sizeof(double),
                                        hipMemcpyHostToDevice, st));
-        sc.tabs_on_device.swap(tabs);
+        sc.tab_key = key;
+        sc.nq = (int)trule.size();
+        sc.nftq = (int)ftq.size();
+        sc.nhinv = (int)hinv.size();
     }
+    const int nq = sc.nq;
+    const int64_t np = ntri * nq;
     if ((stt = ens(sc.pts, (size_t)np * sizeof(double4))) != HSD_OK) return stt;
     if ((stt = ens(sc.spts, (size_t)np * sizeof(double4))) != HSD_OK) return stt;
     if ((stt = ens(sc.keys, (size_t)np * sizeof(int))) != HSD_OK) return stt;
@@ -935,7 +934,7 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
     if (lattice) {
         hipLaunchKernelGGL(k_lattice_out, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
                            sc.fine.as<const double2>(), n2, rule->d_nodes.as<const double>(), N, 1.0 / rule->cube_h,
-                           rule->cube_M, sc.hinv.as<const double>() + hinv.size(), out);
+                           rule->cube_M, sc.hinv.as<const double>() + sc.nhinv, out);
         HSD_HIP_TRY(hipGetLastError());
         if ((stt = mark(5)) != HSD_OK) return stt;
         if (pairs) *pairs = (double)np;
@@ -975,7 +974,7 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
             const dim3 ng((unsigned)((N + 255) / 256)), nb(256);
             if ((stt = e->inv.alloc(ctx, (size_t)N * sizeof(double))) != HSD_OK) return stt;
             hipLaunchKernelGGL(k_phi_inv, ng, nb, 0, st, dirs, rule->d_radii.as<const double>(), n_rad, N, h1, w,
-                               sc.ftq.as<const double2>(), (int)ftq.size(), e->inv.as<double>());
+                               sc.ftq.as<const double2>(), sc.nftq, e->inv.as<double>());
             HSD_HIP_TRY(hipGetLastError());
             // targets grouped by interpolation tile (stable sort: ascending
             // node index within a tile), then cut into work items
