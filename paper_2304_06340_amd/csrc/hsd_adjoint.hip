@@ -44,7 +44,8 @@ constexpr double dcosc_coef(int k) { return ((k & 1) ? 1.0 : -1.0) * (2.0 * k - 
 // (sin x - (1-cos x)/x)/x lose at most about 6 eps / x^2 to cancellation
 // (2.7e-13 relative at x = 0.05); a lower threshold makes the lanes of a
 // wave (different triangles) take the series less often.
-HSD_HD void dsinc_dcosc(double x, double ix, double sx, double cx, double &dsinc, double &dcosc)
+HSD_HD void dsinc_dcosc(double x, double ix, double sx, double cx, double sinc, double cosc, double &dsinc,
+                        double &dcosc)
 {
     if (x < 0.05) {
         const double x2 = x * x;
@@ -57,7 +58,6 @@ HSD_HD void dsinc_dcosc(double x, double ix, double sx, double cx, double &dsinc
         dsinc = ps * x;
         dcosc = pc;
     } else {
-        const double sinc = sx * ix, cosc = (1.0 - cx) * ix;
         dsinc = (cx - sinc) * ix;
         dcosc = (sx - cosc) * ix;
     }
@@ -113,8 +113,8 @@ HSD_HD void pair_factors(double a, double b, double tau, cs64 hu, cs64 hv, doubl
         const double cosc_a = 2.0 * hu.s * hu.s * ia;
         const double cosc_b = 2.0 * hv.s * hv.s * ib;
         double dsa, dca, dsb, dcb;
-        dsinc_dcosc(a, ia, sa, ca, dsa, dca);
-        dsinc_dcosc(b, ib, sb, cb, dsb, dcb);
+        dsinc_dcosc(a, ia, sa, ca, sinc_a, cosc_a, dsa, dca);
+        dsinc_dcosc(b, ib, sb, cb, sinc_b, cosc_b, dsb, dcb);
         F[0] = (cosc_b + cosc_a) * iG;
         F[1] = (sinc_b - sinc_a) * iG;
         Fa[0] = (dca - F[0]) * iG;
@@ -196,8 +196,9 @@ HSD_HD void adjoint_scatter(double nx, double ny, double nz, const double u[3], 
 // per-(triangle, direction) constants c (theta_mid, a/2, b/2) at radius
 // m_p +- h x_k are exp(-i m_p c) exp(-+i h x_k c), with the offsets' phases
 // computed once per direction and the panel centres stepped by
-// exp(-2 i h c); the nodes h - h x_k of panel 0 (small radius, where the
-// product would lose relative accuracy) are evaluated directly.  1/r comes
+// exp(-2 i h c), for every node (the nodes h - h x_k of panel 0 included:
+// their half-gap sines then carry an absolute rounding of the larger angles
+// (h + h x_k) c, as in the forward kernel).  1/r comes
 // from the rule's table of reciprocal radii (the same for all lanes), 1/a
 // and 1/b from per-direction reciprocals.
 HSD_HD void adjoint_lane_sp(const TriRec &T, const double *dirs, const double *iradii, int P, int n, double h,
@@ -240,13 +241,8 @@ HSD_HD void adjoint_lane_sp(const TriRec &T, const double *dirs, const double *i
                     const double r = sg == 0 ? m + hx : m - hx;
                     const int ir = p * n + (sg == 0 ? nh + k : nh - 1 - k);
                     cs64 ph[3];
-                    if (sg == 1 && p == 0) {
 #pragma unroll
-                        for (int c = 0; c < 3; ++c) ph[c] = sincos64(r * fr[c]);
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < 3; ++c) ph[c] = sg == 0 ? pmul(cp[c], bk[c]) : pmulc(cp[c], bk[c]);
-                    }
+                    for (int c = 0; c < 3; ++c) ph[c] = sg == 0 ? pmul(cp[c], bk[c]) : pmulc(cp[c], bk[c]);
                     const double irr = iradii[ir];
                     const int64_t node = d * n_rad + ir;
                     const double W = wd * wtab[ir];
