@@ -151,9 +151,10 @@ hsd_status validate_params(const hsd_params *p)
 }
 
 // Stated relative error of d^2 per form, from the error analysis and the
-// measurements against the FP64 oracle (icospheres of levels 0-7 against
-// S^2): the FP64 direct form is held to 1e-10; the mixed form's FP32 per-pair
-// rounding leaves 5e-8 .. 1.5e-6 on levels 2-7, stated as 5e-6; the NUFFT
+// measurements against the FP64 oracle (icospheres of levels 2-7 against S^2
+// with the 262,144-node rule): the FP64 direct form is held to 1e-10 (it
+// measures below 4e-13); the mixed form's FP32 rounding leaves 1.6e-8 ..
+// 1.4e-7 on those levels (largest at level 5), stated as 5e-7; the NUFFT
 // error is the requested tolerance relative to sum |c_j| per node, amplified
 // by |mu| / |R| (stated as tol * 1e4; the point rule's model error is not
 // included).
