@@ -390,6 +390,16 @@ __global__ void k_predeconv(const double *__restrict__ grid, int n1, const doubl
 // fills 78.6 KB of LDS.  A block stages the box (periodic indices, rows along
 // z), then its threads interpolate the tile's targets from LDS.  Tiles with
 // many targets are cut into several work items, one block each.
+//
+// LDS banks: in 16-byte units a box element sits at x 17^2 + y 17 + z, which
+// is x + y + z mod 16, so at every step of the stencil loop a lane reads the
+// bank class of its stencil origin plus a step offset common to all lanes.
+// Lanes whose origins share a class mod 16 (mod 8 for 128-byte LDS cycles)
+// conflict, while lanes with the same origin read the same addresses (a
+// broadcast).  Within a tile the targets are therefore ordered round-robin
+// over the 16 classes (one target of each class in turn), each class in the
+// order of its origins, so that 16 consecutive threads hold different
+// classes or, where a tile has few classes, mostly the same origins.
 template <int W> constexpr int interp_tile() { return 18 - W > 2 ? 18 - W : 2; }
 
 __device__ __forceinline__ int wrap_index(int m, int n)
@@ -398,25 +408,32 @@ __device__ __forceinline__ int wrap_index(int m, int n)
     return m < 0 ? m + n : m;
 }
 
-// tile key of every target's stencil origin, with its index
+// tile key of every target's stencil origin, with its index, and the
+// origin's place in its tile (b_x TS^2 + b_y TS + b_z) times 16 plus its LDS
+// bank class (lo_x + lo_y + lo_z) mod 16 (see k_interp)
 __global__ __launch_bounds__(256) void k_target_tiles(const double *__restrict__ dirs, const double *__restrict__ radii,
                                                       int n_rad, int64_t N, double scale, int w, int H, int TS,
-                                                      int nt1, int *__restrict__ keys, int *__restrict__ idx)
+                                                      int nt1, int *__restrict__ keys, int *__restrict__ idx,
+                                                      int *__restrict__ bank)
 {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N) return;
     const int64_t d = k / n_rad;
     const double r = radii[k - d * n_rad];
-    int key = 0;
+    int key = 0, sum = 0, place = 0;
     for (int a = 0; a < 3; ++a) {
         const double u = r * dirs[3 * d + a] * scale;
         const int lo = (int)ceil(u - 0.5 * w);
         int c = (lo + H) / TS;
         c = c < 0 ? 0 : (c >= nt1 ? nt1 - 1 : c);
         key = key * nt1 + c;
+        sum += lo;
+        const int b = lo + H - c * TS;
+        place = place * TS + (b < 0 ? 0 : (b >= TS ? TS - 1 : b));
     }
     keys[k] = key;
     idx[k] = (int)k;
+    bank[k] = (place << 4) | (sum & 15);
 }
 
 template <int W>
@@ -978,13 +995,15 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
             HSD_HIP_TRY(hipGetLastError());
             // targets grouped by interpolation tile (stable sort: ascending
             // node index within a tile), then cut into work items
-            DevBuf keys, keys2, idx, tmp;
+            DevBuf keys, keys2, idx, tmp, bank;
             if ((stt = keys.alloc(ctx, (size_t)N * sizeof(int))) != HSD_OK) return stt;
+            if ((stt = bank.alloc(ctx, (size_t)N * sizeof(int))) != HSD_OK) return stt;
             if ((stt = keys2.alloc(ctx, (size_t)N * sizeof(int))) != HSD_OK) return stt;
             if ((stt = idx.alloc(ctx, (size_t)N * sizeof(int))) != HSD_OK) return stt;
             if ((stt = e->order.alloc(ctx, (size_t)N * sizeof(int))) != HSD_OK) return stt;
             hipLaunchKernelGGL(k_target_tiles, ng, nb, 0, st, dirs, rule->d_radii.as<const double>(), n_rad, N,
-                               (double)n2 * h1 / (2.0 * kPi), w, H, TS, nt1, keys.as<int>(), idx.as<int>());
+                               (double)n2 * h1 / (2.0 * kPi), w, H, TS, nt1, keys.as<int>(), idx.as<int>(),
+                               bank.as<int>());
             HSD_HIP_TRY(hipGetLastError());
             int key_bits = 1;
             while (((int64_t)1 << key_bits) < (int64_t)nt1 * nt1 * nt1) ++key_bits;
@@ -994,9 +1013,43 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
             if ((stt = tmp.alloc(ctx, std::max<size_t>(tmp_bytes, 8))) != HSD_OK) return stt;
             HSD_HIP_TRY(rocprim::radix_sort_pairs(tmp.ptr, tmp_bytes, keys.as<int>(), keys2.as<int>(), idx.as<int>(),
                                                   e->order.as<int>(), (unsigned int)N, 0, key_bits, st));
-            std::vector<int> sk((size_t)N);
+            std::vector<int> sk((size_t)N), ord((size_t)N), bk((size_t)N);
             HSD_HIP_TRY(hipMemcpyAsync(sk.data(), keys2.ptr, (size_t)N * sizeof(int), hipMemcpyDeviceToHost, st));
+            HSD_HIP_TRY(hipMemcpyAsync(ord.data(), e->order.ptr, (size_t)N * sizeof(int), hipMemcpyDeviceToHost, st));
+            HSD_HIP_TRY(hipMemcpyAsync(bk.data(), bank.ptr, (size_t)N * sizeof(int), hipMemcpyDeviceToHost, st));
             HSD_HIP_TRY(hipStreamSynchronize(st));
+            // within each tile, targets round-robin over their LDS bank
+            // classes, each class ordered by stencil origin (stable), see
+            // k_interp
+            {
+                std::vector<int> seg;
+                for (int64_t a = 0; a < N;) {
+                    int64_t b = a + 1;
+                    while (b < N && sk[(size_t)b] == sk[(size_t)a]) ++b;
+                    if (b - a > 1) {
+                        int cnt[16] = {}, start[17] = {};
+                        for (int64_t q = a; q < b; ++q) ++cnt[bk[(size_t)ord[(size_t)q]] & 15];
+                        int mx = 0;
+                        for (int c = 0; c < 16; ++c) {
+                            start[c + 1] = start[c] + cnt[c];
+                            mx = std::max(mx, cnt[c]);
+                        }
+                        seg.assign((size_t)(b - a), 0);
+                        int fill[16];
+                        for (int c = 0; c < 16; ++c) fill[c] = start[c];
+                        for (int64_t q = a; q < b; ++q) seg[(size_t)fill[bk[(size_t)ord[(size_t)q]] & 15]++] = ord[(size_t)q];
+                        for (int c = 0; c < 16; ++c)
+                            std::stable_sort(seg.begin() + start[c], seg.begin() + start[c + 1],
+                                             [&](int x, int y) { return bk[(size_t)x] < bk[(size_t)y]; });
+                        int64_t o = a;
+                        for (int rr = 0; rr < mx; ++rr)
+                            for (int c = 0; c < 16; ++c)
+                                if (rr < cnt[c]) ord[(size_t)o++] = seg[(size_t)(start[c] + rr)];
+                    }
+                    a = b;
+                }
+            }
+            HSD_HIP_TRY(hipMemcpyAsync(e->order.ptr, ord.data(), (size_t)N * sizeof(int), hipMemcpyHostToDevice, st));
             constexpr int kItemTargets = 1024;   // targets per interpolation work item (at most)
             std::vector<int4> it;
             for (int64_t a = 0; a < N;) {
