@@ -1059,6 +1059,9 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
                     it.push_back(make_int4(sk[(size_t)a], (int)c, (int)std::min<int64_t>(b, c + kItemTargets), 0));
                 a = b;
             }
+            // largest items first (blocks start roughly in launch order, so
+            // the long ones do not form the tail of the launch)
+            std::stable_sort(it.begin(), it.end(), [](const int4 &x, const int4 &y) { return x.z - x.y > y.z - y.y; });
             e->nitems = (int)it.size();
             if ((stt = e->items.alloc(ctx, std::max<size_t>(it.size(), 1) * sizeof(int4))) != HSD_OK) return stt;
             if (!it.empty())
