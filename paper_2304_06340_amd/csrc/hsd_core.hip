@@ -135,9 +135,10 @@ hsd_status validate_params(const hsd_params *p)
         return HSD_EINVAL;
     }
     // the FP64 series is summed through the ninth power in the per-node
-    // kernels and through the seventh in the wave-per-direction kernel
-    // (first omitted term below 1e-16 of the leading 1/2 for G < 0.05), the
-    // mixed form's through the 11th (below 5e-12 for G < 0.75)
+    // kernels and in the wave-per-direction kernel through the seventh
+    // (first omitted term below 1e-16 of the leading 1/2 for G < 0.05), or
+    // the fifth for thresholds up to 0.015 (below 4e-15 there), the mixed
+    // form's through the 11th (below 5e-12 for G < 0.75)
     const double tau_max = p->form == HSD_FORM_MIXED ? kMixedTau : 0.05;
     if (!(p->taylor_tau > 0.0) || p->taylor_tau > tau_max) {
         set_error("taylor_tau must be in (0, %g] for this form (got %g)", tau_max, p->taylor_tau);

@@ -44,8 +44,11 @@ constexpr double kGapFloor32 = 1e-18;
 // Re = sum_m ce[m] r^(2m), Im = r sum_m co[m] r^(2m) (see series_coefs).
 // FP64 form: series through r^7; the first omitted term is below
 // 9 G^8 / 10! of the leading 1/2, 1e-16 at the largest threshold the form
-// accepts (G < 0.05) and 2.5e-22 at the default 0.01
+// accepts (G < 0.05) and 2.5e-22 at the default 0.01.  For thresholds up to
+// kTauNC3 the consumer sums only through r^5 (first omitted term below
+// 7 G^6 / 8! of the leading 1/2: 4e-15 at 0.015, 3.5e-16 at 0.01).
 constexpr int kNC64 = 4;
+constexpr double kTauNC3 = 0.015;
 constexpr int kNC32 = (kMixedSeriesN + 1) / 2;  // through r^kMixedSeriesN (mixed form)
 struct Scal64 { double rthr, pad; double ce[kNC64], co[kNC64]; };   // ce, co carry the factor |J|
 struct Scal32 { float rthr, Ka, Kb, c0lo; float ce[kNC32], co[kNC32]; };   // Ka, Kb, ce, co carry |J|
@@ -107,14 +110,15 @@ HSD_HD void series_coefs(double ac, double bc, double scale, double ce[NC], doub
     }
 }
 
-// Even/odd polynomial of the series at r (r2 = r^2): returns Re, Im / r.
-template <typename T>
+// Even/odd polynomial of the series at r (r2 = r^2) through its first NC
+// coefficients of each parity: returns Re, Im / r.
+template <int NC, typename T>
 HSD_HD void series_eval(const T ce[kNC64], const T co[kNC64], T r2, T &pe, T &po)
 {
-    pe = ce[kNC64 - 1];
-    po = co[kNC64 - 1];
+    pe = ce[NC - 1];
+    po = co[NC - 1];
 #pragma unroll
-    for (int m = kNC64 - 2; m >= 0; --m) {
+    for (int m = NC - 2; m >= 0; --m) {
         pe = pe * r2 + ce[m];
         po = po * r2 + co[m];
     }
@@ -181,7 +185,7 @@ HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, i
     const double aJ = fabs(td.J);
     const double rab = rcp64(td.ac * td.bc);
     const double t = 2.0 * aJ * td.iG;
-    const double ska = __builtin_sqrt(t * (td.bc * rab)), skb = __builtin_sqrt(t * (td.ac * rab));
+    const double ska = sqrt_pos64(t * (td.bc * rab)), skb = sqrt_pos64(t * (td.ac * rab));
     if (td.J < 0.0) Bk[0] = cs64{-Bk[0].c, -Bk[0].s};
 #pragma unroll
     for (int q = 0; q < PG; ++q) {
@@ -202,33 +206,57 @@ HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, i
 // only for r G >= tau) turns into a relative error below ~eps / tau, the
 // same class as the branch's own cancellation; below tau only the
 // theta_mid phase enters.
+//
+// The series branch replaces the closed one where r < tau / G.  Within a
+// lane the slot (pl 0, minus) has the smallest radius; r_others is the
+// smallest radius of any other slot over the whole wave ((2 w0 + 1) h +
+// h x_0), so when the triangle's threshold is not above it only that slot
+// can take the series, and the others skip their compare.  nc3: thresholds
+// up to kTauNC3, series through r^5.
 template <int PG>
 HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 (*Cp)[3], double h,
-                      double hx, int pbase, double *acc_re, double *acc_im)
+                      double hx, int pbase, double r_others, bool nc3, double *acc_re, double *acc_im)
 {
+    constexpr int NS = 2 * PG;
+    double Yr[NS], Xr[NS], rs[NS];
 #pragma unroll
     for (int pl = 0; pl < PG; ++pl) {
-        const int p = pbase + pl;
-        const double m = (double)(2 * p + 1) * h;
+        const double m = (double)(2 * (pbase + pl) + 1) * h;
 #pragma unroll
         for (int sg = 0; sg < 2; ++sg) {
             const int slot = 2 * pl + sg;
-            const double r = sg == 0 ? m + hx : m - hx;
+            rs[slot] = sg == 0 ? m + hx : m - hx;
             // E[1], E[2] carry sqrt(K_a), sqrt(K_b) (see produce64)
-            cs64 E[3];
+            const cs64 E1 = sg == 0 ? pmul(Cp[pl][1], Bk[1]) : pmulc(Cp[pl][1], Bk[1]);
+            const cs64 E2 = sg == 0 ? pmul(Cp[pl][2], Bk[2]) : pmulc(Cp[pl][2], Bk[2]);
+            Yr[slot] = __builtin_fma(E2.s, E2.s, E1.s * E1.s);
+            Xr[slot] = __builtin_fma(E2.s, E2.c, -(E1.s * E1.c));
+        }
+    }
+    auto series = [&](int slot) {
+        const double r = rs[slot], r2 = r * r;
+        double pe, po;
+        if (nc3)
+            series_eval<3>(sc.ce, sc.co, r2, pe, po);
+        else
+            series_eval<kNC64>(sc.ce, sc.co, r2, pe, po);
+        Yr[slot] = r2 * pe;
+        Xr[slot] = r2 * r * po;
+    };
+    if (rs[1] < sc.rthr) series(1);
+    if (sc.rthr > r_others) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) E[c] = sg == 0 ? pmul(Cp[pl][c], Bk[c]) : pmulc(Cp[pl][c], Bk[c]);
-            double Yr = __builtin_fma(E[2].s, E[2].s, E[1].s * E[1].s);
-            double Xr = __builtin_fma(E[2].s, E[2].c, -(E[1].s * E[1].c));
-            if (r < sc.rthr) {
-                const double r2 = r * r;
-                double pe, po;
-                series_eval(sc.ce, sc.co, r2, pe, po);
-                Yr = r2 * pe;
-                Xr = r2 * r * po;
-            }
-            acc_re[slot] = __builtin_fma(E[0].c, Yr, __builtin_fma(E[0].s, Xr, acc_re[slot]));
-            acc_im[slot] = __builtin_fma(E[0].c, Xr, __builtin_fma(-E[0].s, Yr, acc_im[slot]));
+        for (int slot = 0; slot < NS; ++slot)
+            if (slot != 1 && rs[slot] < sc.rthr) series(slot);
+    }
+#pragma unroll
+    for (int pl = 0; pl < PG; ++pl) {
+#pragma unroll
+        for (int sg = 0; sg < 2; ++sg) {
+            const int slot = 2 * pl + sg;
+            const cs64 E0 = sg == 0 ? pmul(Cp[pl][0], Bk[0]) : pmulc(Cp[pl][0], Bk[0]);
+            acc_re[slot] = __builtin_fma(E0.c, Yr[slot], __builtin_fma(E0.s, Xr[slot], acc_re[slot]));
+            acc_im[slot] = __builtin_fma(E0.c, Xr[slot], __builtin_fma(-E0.s, Yr[slot], acc_im[slot]));
         }
     }
 }
@@ -414,6 +442,8 @@ __device__ __forceinline__ void direct_wave_body(
     const int po = lane >> 4, sgl = (lane >> 3) & 1;
     float rf[F64 ? 1 : NS], r2f[F64 ? 1 : NS];
     double r2d[F64 ? 1 : NS];
+    const double r_others = (double)(2 * w0 + 1) * h + hx_tab[0];   // see consume64
+    const bool nc3 = tau <= kTauNC3;
     if constexpr (!F64) mixed_lane_radii<PG>(w0, po, sgl, h, hx, rf, r2f, r2d);
     auto &L = lds[w];
 
@@ -450,7 +480,7 @@ __device__ __forceinline__ void direct_wave_body(
         wave_lds_sync();
         for (int t = 0; t < nvalid; ++t) {
             if constexpr (F64)
-                consume64<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][g * PG], h, hx, pbase, acc_re, acc_im);
+                consume64<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][g * PG], h, hx, pbase, r_others, nc3, acc_re, acc_im);
             else
                 consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1, acc_re, acc_im, tot_re,
                               tot_im);
@@ -624,7 +654,8 @@ static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, dou
                     if (F64) {
                         auto &L = b64[0];
                         consume64<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][g * PG], h, hx_tab[k], pbase,
-                                      &are[lane * NS], &aim[lane * NS]);
+                                      (double)(2 * w0 + 1) * h + hx_tab[0], tau <= kTauNC3, &are[lane * NS],
+                                      &aim[lane * NS]);
                     } else {
                         auto &L = b32[0];
                         consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1, &fre[lane * NS],

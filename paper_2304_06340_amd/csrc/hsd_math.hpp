@@ -187,6 +187,28 @@ HSD_HD double rcp64(double x)
 #endif
 }
 
+// Square root of x >= 0 (0 for x = 0) from the hardware reciprocal square
+// root and two Newton-Raphson corrections of the root (Goldschmidt form),
+// without the library's scaling for denormal and special inputs: used where
+// x is a positive normal number or zero.
+HSD_HD double sqrt_pos64(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, hh = 0.5 * y;
+    const double e = __builtin_fma(-hh, g, 0.5);
+    g = __builtin_fma(g, e, g);
+    hh = __builtin_fma(hh, e, hh);
+    double d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, hh, g);
+    d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, hh, g);
+    return x > 0.0 ? g : 0.0;
+#else
+    return __builtin_sqrt(x);
+#endif
+}
+
 HSD_HD float rcp32(float x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
