@@ -88,6 +88,34 @@ def test_transform_on_rule_elementwise(hsd_ctx, orc, spec, form):
         assert err.max() <= 2e-5 * _area(v, f), err.max()
 
 
+@pytest.mark.parametrize("spec", [
+    dict(r_max=32.0, n_panels=16, n_per_panel=16, n_cos=4, n_phi=8),   # two panels per lane, one wave per direction
+    dict(r_max=16.0, n_panels=8, n_per_panel=16, n_cos=4, n_phi=8),    # one panel per lane
+    dict(r_max=64.0, n_panels=32, n_per_panel=16, n_cos=3, n_phi=4),   # two waves per direction
+])
+@pytest.mark.parametrize("tau", [0.005, 0.015, 0.05])
+def test_wave_kernel_series_thresholds(hsd_ctx, orc, spec, tau):
+    """The wave kernel's series branch at thresholds on both sides of 0.015
+    (series through r^5 up to it, r^7 above) and large enough that triangles
+    with a small phase spread take the series in slots other than the
+    smallest-radius one: element by element against the oracle at the same
+    threshold (a level-3 mesh: gaps down to a few 1e-3)."""
+    rng = np.random.default_rng(11)
+    v, f = icosphere(3)
+    v = rotate(perturb_radial(v, 0.01, rng), random_rotation(rng))
+    g, o = _rules(hsd_ctx, orc, spec)
+    mesh = hsd.Mesh(hsd_ctx, v, f)
+    got = hsd.transform_rule(hsd_ctx, mesh, g, hsd.Params(taylor_tau=tau))
+    ref = orc.transform(v, f, o.nodes, tau=tau)
+    h = spec["r_max"] / spec["n_panels"] / 2
+    err = np.abs(got - ref)
+    tol = _mu_tol(v, f, o.nodes, tau=tau, h=h)
+    print(f"tau {tau}: max err/tol {np.max(err / tol):.3f}")
+    assert np.all(err <= tol), np.max(err / tol)
+    mesh.close()
+    g.close()
+
+
 def test_general_kernel_special_cases(hsd_ctx, orc):
     """Nodes along a face normal (all gaps 0), orthogonal to an edge (one gap
     0), tiny |xi| (series branch), degenerate triangles, random nodes."""
