@@ -123,15 +123,20 @@ __global__ void k_nufft_points(const TriRec *__restrict__ A, int64_t nA, const T
 }
 
 // Bin offsets from the sorted keys: offs[b] = first position whose key is
-// >= b (offs[nbins] = np).  Position i writes the bins in (key[i-1], key[i]],
-// so every entry has exactly one writer.
+// >= b (offs[nbins] = np), one thread per bin by binary search (clustered
+// points leave long runs of empty bins, which a thread per point would
+// write one by one).
 __global__ void k_bin_offsets(const int *__restrict__ skeys, int64_t np, int nbins, int *__restrict__ offs)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > np) return;
-    const int prev = i == 0 ? -1 : skeys[i - 1];
-    const int cur = i == np ? nbins : skeys[i];
-    for (int b = prev + 1; b <= cur; ++b) offs[b] = (int)i;
+    const int b = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (b > nbins) return;
+    int64_t lo = 0, hi = np;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (skeys[mid] < b) lo = mid + 1;
+        else hi = mid;
+    }
+    offs[b] = (int)lo;
 }
 
 __global__ void k_iota(int *__restrict__ idx, int64_t np)
@@ -891,7 +896,7 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
                            sc.perm.as<const int>(), np, sc.spts.as<double4>());
         HSD_HIP_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_bin_offsets, dim3((unsigned)((np + 1 + 255) / 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_bin_offsets, dim3((unsigned)(((int64_t)nbins + 1 + 255) / 256)), dim3(256), 0, st,
                        sc.keys2.as<const int>(), np, nbins, sc.offs.as<int>());
     HSD_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_tile_items, dim3((unsigned)((ntiles + 1 + 255) / 256)), dim3(256), 0, st,
