@@ -83,6 +83,7 @@ struct FftPlan;
 struct NufftScratch {
     DevBuf pts, spts, keys, keys2, iota, offs, perm, sorttmp, grid1, fine, tri, ftq, hinv;
     DevBuf titems, tstart, itile, tilebuf, scantmp;   // spread work items per tile
+    DevBuf heavy;     // [0] = count, then the tiles with more than one work item
     std::unique_ptr<FftPlan> plan;
     // stage timing of the last transform (recorded when the context asks):
     // events at the stage boundaries and each stage's algorithmic bytes

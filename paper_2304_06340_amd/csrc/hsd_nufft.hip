@@ -166,10 +166,12 @@ __global__ void k_gather_points(const double4 *__restrict__ pts, const int *__re
 //    Work items: a tile whose neighbourhood holds more than kItemChunks
 //    chunks gets several items, item s taking the chunks numbered
 //    [s kItemChunks, (s + 1) kItemChunks) of the tile's sequence (bins in
-//    order, chunks of 64 points); each writes a partial tile, summed in item
-//    order by k_tile_reduce.  Clustered points (a whole mesh in a few bins, as on the
+//    order, chunks of 64 points); each writes a partial tile, summed by
+//    k_tile_reduce (eighths of the item range in item order, then the eighths
+//    in order).  Clustered points (a whole mesh in a few bins, as on the
 //    cube lattice) then spread over many waves instead of a few long ones.
-//    Sum order per grid point: item, then bin, then point order.
+//    Sum order per grid point: fixed (items as above, then bin, then point
+//    order).
 // --------------------------------------------------------------------------
 constexpr int kItemChunks = 64;   // candidate chunks per work item (at most)
 
@@ -180,13 +182,18 @@ __device__ __forceinline__ void tile_of(int t, int nbx, int &bx, int &by, int &b
     bx = t / (nbx * nbx);
 }
 
-// titems[t] = number of work items of tile t (>= 1); titems[ntiles] = 0
-__global__ void k_tile_items(const int *__restrict__ offs, int nbx, int *__restrict__ titems)
+// titems[t] = number of work items of tile t (>= 1); titems[ntiles] = 0;
+// heavy[0] (the count of tiles with several items) = 0
+__global__ void k_tile_items(const int *__restrict__ offs, int nbx, int *__restrict__ titems, int *__restrict__ heavy)
 {
     const int ntiles = nbx * nbx * nbx;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t > ntiles) return;
-    if (t == ntiles) { titems[t] = 0; return; }
+    if (t == ntiles) {
+        titems[t] = 0;
+        heavy[0] = 0;
+        return;
+    }
     int bx, by, bz;
     tile_of(t, nbx, bx, by, bz);
     int64_t chunks = 0;
@@ -201,12 +208,16 @@ __global__ void k_tile_items(const int *__restrict__ offs, int nbx, int *__restr
     titems[t] = (int)(chunks > 0 ? (chunks + kItemChunks - 1) / kItemChunks : 1);
 }
 
-// itile[item] = its tile, for the items of every tile (tstart = exclusive scan)
-__global__ void k_item_map(const int *__restrict__ tstart, int ntiles, int *__restrict__ itile)
+// itile[item] = its tile, for the items of every tile (tstart = exclusive
+// scan); the tiles with several items listed in heavy[1..heavy[0]] (in any
+// order: each is reduced on its own, in a fixed order)
+__global__ void k_item_map(const int *__restrict__ tstart, int ntiles, int *__restrict__ itile,
+                           int *__restrict__ heavy)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ntiles) return;
     for (int i = tstart[t]; i < tstart[t + 1]; ++i) itile[i] = t;
+    if (tstart[t + 1] - tstart[t] > 1) heavy[1 + atomicAdd(&heavy[0], 1)] = t;
 }
 
 __global__ __launch_bounds__(64) void k_spread(const double4 *__restrict__ spts, const int *__restrict__ offs,
@@ -329,30 +340,72 @@ __global__ __launch_bounds__(64) void k_spread(const double4 *__restrict__ spts,
     }
 }
 
-// Sum of the partial tiles of tiles with several work items, in item order.
-__global__ __launch_bounds__(64) void k_tile_reduce(const double *__restrict__ tilebuf, const int *__restrict__ tstart,
-                                                    int nbx, int n1, double *__restrict__ grid)
+// Sum of the partial tiles of the tiles with several work items (the list
+// in heavy): per tile with more than kReduceWaves items, the 8 waves of a
+// block sum consecutive eighths of its items in item order, then wave 0 adds
+// the eight partial sums in wave order (a tile in a cluster of points can
+// have hundreds of items); fewer items are summed by wave 0 in item order.
+// Either way the order is fixed.  Blocks stride over the list.
+constexpr int kReduceWaves = 8;
+__global__ __launch_bounds__(64 * kReduceWaves) void k_tile_reduce(const double *__restrict__ tilebuf,
+                                                                   const int *__restrict__ tstart,
+                                                                   const int *__restrict__ heavy, int nbx, int n1,
+                                                                   double *__restrict__ grid)
 {
-    const int tile = blockIdx.x;
-    const int i0 = tstart[tile], i1 = tstart[tile + 1];
-    if (i1 - i0 <= 1) return;   // written by its only item
-    const int lane = threadIdx.x, tx = lane & 7, ty = lane >> 3;
-    double acc[kBin];
+    __shared__ double part[kReduceWaves][kBin][64];
+    const int nh = heavy[0];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, tx = lane & 7, ty = lane >> 3;
+    for (int hi = blockIdx.x; hi < nh; hi += gridDim.x) {   // block-uniform
+        const int tile = heavy[1 + hi];
+        const int i0 = tstart[tile];
+        const int64_t n = tstart[tile + 1] - i0;
+        int bx, by, bz;
+        tile_of(tile, nbx, bx, by, bz);
+        const int lx = bx * kBin + tx, ly = by * kBin + ty, z0 = bz * kBin;
+        double acc[kBin];
+        if (n <= kReduceWaves) {   // block-uniform
+            if (w != 0) continue;
 #pragma unroll
-    for (int z = 0; z < kBin; ++z) acc[z] = 0.0;
-    for (int i = i0; i < i1; ++i) {
-        const double *src = tilebuf + (int64_t)i * (kBin * kBin * kBin) + lane * kBin;
+            for (int z = 0; z < kBin; ++z) acc[z] = 0.0;
+            for (int i = i0; i < i0 + (int)n; ++i) {
+                const double *src = tilebuf + (int64_t)i * (kBin * kBin * kBin) + lane * kBin;
 #pragma unroll
-        for (int z = 0; z < kBin; ++z) acc[z] += src[z];
-    }
-    int bx, by, bz;
-    tile_of(tile, nbx, bx, by, bz);
-    const int lx = bx * kBin + tx, ly = by * kBin + ty, z0 = bz * kBin;
-    if (lx < n1 && ly < n1) {
-        double *col = grid + ((int64_t)lx * n1 + ly) * n1;
+                for (int z = 0; z < kBin; ++z) acc[z] += src[z];
+            }
+            if (lx < n1 && ly < n1) {
+                double *col = grid + ((int64_t)lx * n1 + ly) * n1;
 #pragma unroll
-        for (int z = 0; z < kBin; ++z)
-            if (z0 + z < n1) col[z0 + z] = acc[z];
+                for (int z = 0; z < kBin; ++z)
+                    if (z0 + z < n1) col[z0 + z] = acc[z];
+            }
+            continue;
+        }
+        const int a = i0 + (int)(n * w / kReduceWaves), b = i0 + (int)(n * (w + 1) / kReduceWaves);
+#pragma unroll
+        for (int z = 0; z < kBin; ++z) acc[z] = 0.0;
+        for (int i = a; i < b; ++i) {
+            const double *src = tilebuf + (int64_t)i * (kBin * kBin * kBin) + lane * kBin;
+#pragma unroll
+            for (int z = 0; z < kBin; ++z) acc[z] += src[z];
+        }
+#pragma unroll
+        for (int z = 0; z < kBin; ++z) part[w][z][lane] = acc[z];
+        __syncthreads();
+        if (w == 0) {
+#pragma unroll
+            for (int z = 0; z < kBin; ++z) {
+                double t = part[0][z][lane];
+                for (int ww = 1; ww < kReduceWaves; ++ww) t += part[ww][z][lane];
+                acc[z] = t;
+            }
+            if (lx < n1 && ly < n1) {
+                double *col = grid + ((int64_t)lx * n1 + ly) * n1;
+#pragma unroll
+                for (int z = 0; z < kBin; ++z)
+                    if (z0 + z < n1) col[z0 + z] = acc[z];
+            }
+        }
+        __syncthreads();   // part is rewritten by the next tile
     }
 }
 
@@ -665,7 +718,7 @@ size_t NufftScratch::bytes() const
 {
     size_t b = 0;
     for (const DevBuf *x : {&pts, &spts, &keys, &keys2, &iota, &offs, &perm, &sorttmp, &grid1, &fine, &tri, &ftq,
-                            &hinv, &titems, &tstart, &itile, &tilebuf, &scantmp})
+                            &hinv, &titems, &tstart, &itile, &tilebuf, &scantmp, &heavy})
         b += x->bytes;
     if (plan) b += plan->tw.bytes + plan->plan.bytes;
     return b;
@@ -675,7 +728,7 @@ void NufftScratch::release()
 {
     tab_key.clear();
     for (DevBuf *x : {&pts, &spts, &keys, &keys2, &iota, &offs, &perm, &sorttmp, &grid1, &fine, &tri, &ftq, &hinv,
-                      &titems, &tstart, &itile, &tilebuf, &scantmp})
+                      &titems, &tstart, &itile, &tilebuf, &scantmp, &heavy})
         x->release();
     plan.reset();
 }
@@ -746,7 +799,7 @@ int64_t nufft_footprint(double X, const hsd_rule *rule, const hsd_params *p, int
     const int64_t N = rule->n_nodes;
     int64_t b = np * (32 + 32 + 4 * 4)                        // points (raw, sorted), keys, iota, permutation
                 + 2 * np * 4 + 2 * (nbins + 1) * 4 + (1 << 20)   // sort and scan temporaries (bounded)
-                + (nbins + 1) * 4 * 3 + items * 4
+                + (nbins + 1) * 4 * 4 + items * 4
                 + items * (int64_t)kBin * kBin * kBin * 8        // partial tiles
                 + (int64_t)z.n1 * z.n1 * z.n1 * 8                 // spread grid
                 + (int64_t)z.n2 * z.n2 * z.n2 * 16                // FFT grid
@@ -857,6 +910,7 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
                                         (size_t)ntiles + 1, rocprim::plus<int>(), st));
     if ((stt = ens(sc.scantmp, scan_bytes)) != HSD_OK) return stt;
     if ((stt = ens(sc.titems, ((size_t)ntiles + 1) * sizeof(int))) != HSD_OK) return stt;
+    if ((stt = ens(sc.heavy, ((size_t)ntiles + 1) * sizeof(int))) != HSD_OK) return stt;
     if ((stt = ens(sc.tstart, ((size_t)ntiles + 1) * sizeof(int))) != HSD_OK) return stt;
     if ((stt = ens(sc.itile, (size_t)max_items * sizeof(int))) != HSD_OK) return stt;
     if ((stt = ens(sc.tilebuf, (size_t)max_items * kBin * kBin * kBin * sizeof(double))) != HSD_OK) return stt;
@@ -900,20 +954,21 @@ hsd_status nufft_transform_rule(hsd_ctx *ctx, hipStream_t st, NufftScratch &sc, 
                        sc.keys2.as<const int>(), np, nbins, sc.offs.as<int>());
     HSD_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_tile_items, dim3((unsigned)((ntiles + 1 + 255) / 256)), dim3(256), 0, st,
-                       sc.offs.as<const int>(), nbx, sc.titems.as<int>());
+                       sc.offs.as<const int>(), nbx, sc.titems.as<int>(), sc.heavy.as<int>());
     HSD_HIP_TRY(hipGetLastError());
     HSD_HIP_TRY(rocprim::exclusive_scan(sc.scantmp.ptr, scan_bytes, sc.titems.as<const int>(), sc.tstart.as<int>(), 0,
                                         (size_t)ntiles + 1, rocprim::plus<int>(), st));
     hipLaunchKernelGGL(k_item_map, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, st,
-                       sc.tstart.as<const int>(), ntiles, sc.itile.as<int>());
+                       sc.tstart.as<const int>(), ntiles, sc.itile.as<int>(), sc.heavy.as<int>());
     HSD_HIP_TRY(hipGetLastError());
     if ((stt = mark(1)) != HSD_OK) return stt;
     hipLaunchKernelGGL(k_spread, dim3((unsigned)max_items), dim3(64), 0, st, sc.spts.as<const double4>(),
                        sc.offs.as<const int>(), sc.tstart.as<const int>(), sc.itile.as<const int>(), nbx, n1, h1,
                        0.5 * w, beta, sc.grid1.as<double>(), sc.tilebuf.as<double>());
     HSD_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)ntiles), dim3(64), 0, st, sc.tilebuf.as<const double>(),
-                       sc.tstart.as<const int>(), nbx, n1, sc.grid1.as<double>());
+    hipLaunchKernelGGL(k_tile_reduce, dim3((unsigned)std::min<int64_t>(ntiles, 2048)), dim3(64 * kReduceWaves), 0, st,
+                       sc.tilebuf.as<const double>(), sc.tstart.as<const int>(), sc.heavy.as<const int>(), nbx, n1,
+                       sc.grid1.as<double>());
     HSD_HIP_TRY(hipGetLastError());
     if ((stt = mark(2)) != HSD_OK) return stt;
     // the spread grid is zero beyond |l - n1/2| > X / h1 + w / 2 (all points
