@@ -76,24 +76,25 @@ def flops_per_pair(spec, form="fp64") -> float:
     """Algorithmic FLOPs (FMA = 2) per triangle-node pair of the
     wave-per-direction direct-sum kernel (16-node panels), counted from its
     source along the closed branch (the series branch replaces it for the
-    pairs with a small phase spread).
+    pairs with a small phase spread).  A wave covers 8 PG panels, 128 PG
+    nodes of one direction.
 
     FP64 form, consumer per node: 3 phase products (6 each) + the closed
     branch's two numerators from the sqrt(K)-scaled half-gap phases (2 MUL +
     2 FMA = 6) + complex multiply-accumulate (8)                          = 32
     one FP64 sin/cos with its argument (turn-table reduction, degree-9/8
         polynomials, rotation)                                             = 30
-    producer, per (triangle, lane), once per batch of 8 triangles:
-        dot products, gaps and the phase constants (20) + 3 (1 + PG) sin/cos;
-        with one wave per direction (16 panels, PG = 2) the second panel's
-        phase is a product instead: 3 (2 x 30 + 12) + 20                   = 236
-        sqrt(K_a), sqrt(K_b) (reciprocal, products, two square roots: 10)
-        and the scaling of the two half-gap centre rows (4 PG)             = 10 + 4 PG
-    series coefficients (through r^7) and threshold, once per triangle
-        (shared by its 8 lanes)                                            = 46
+    per (triangle, wave), once:
+        record: dot products, gaps and phase constants (20), sqrt(K_a),
+        sqrt(K_b) (reciprocal, products, two square roots: 10), series
+        coefficients through r^7 and threshold (46)                        = 76
+        8 half-node lanes: 3 sin/cos, the two sqrt(K) scalings (4) and the
+        series value of the wave's smallest radius (through r^5: 12)       = 106 each
+        8 panel-centre lanes: 3 PG sin/cos, or with one wave per direction
+        (PG = 2) 3 sin/cos and the second panel's phase as a product with
+        the square of the first panel's phase: 3 (30 + 12)                 = 126 each
     running-sum merges: 2 * 2 PG adds per lane every 32 triangles.
-    A lane owns 2 PG nodes and consumes 8 triangles per batch, so per pair:
-        32 + (producer + 46 / 8) / (16 PG) + 1 / 16.
+    Per pair: 32 + (8 * 106 + 8 * panel lane + 76) / (128 PG) + 1 / 16.
 
     Mixed form (FP32 node arithmetic): consumer 34 per node (the K factors
     applied to the phase sines: 2 more MUL); producer 20 + 3 (1 + PG) FP32
@@ -106,9 +107,8 @@ def flops_per_pair(spec, form="fp64") -> float:
     if form == "mixed":
         return 34.0 + (20.0 + 3 * (1 + PG) * 36.0 + 60.0 / 8) / (16 * PG) + 2.0 / 8
     one_wave = P == 8 * PG
-    producer = 3 * (2 * 30.0 + 12.0) + 20.0 if (one_wave and PG == 2) else 3 * (1 + PG) * 30.0 + 20.0
-    producer += 10.0 + 4 * PG
-    return 32.0 + (producer + 46.0 / 8) / (16 * PG) + 1.0 / 16
+    panel_lane = 3 * (30.0 + 12.0) if (one_wave and PG == 2) else 3 * PG * 30.0
+    return 32.0 + (8 * 106.0 + 8 * panel_lane + 76.0) / (128 * PG) + 1.0 / 16
 
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E

@@ -9,20 +9,25 @@
 //
 //   * a wave owns one direction n and 8*PG consecutive panels; lane
 //     (k, g) = (lane % 8, lane / 8) owns the node pair m_p +- h x_k of its
-//     PG panels p = w0 + g*PG + pl (2*PG nodes);
-//   * triangles are processed in batches of 8.  Producer step: lane
-//     (t, j) = (lane / 8, lane % 8) computes, for triangle t of the batch,
-//     exp(-i h x_j c) and the panel-centre phases exp(-i m_p c) of its PG
-//     panels (panels w0 + j*PG + q in the FP64 form, w0 + j + 8 q in the
-//     mixed form), for the three constants c = theta_mid, a/2, b/2 of the
-//     triangle and direction, and stores them with the triangle's scale
-//     factors in LDS;
+//     PG panels (2*PG nodes);
+//   * FP64 form: per block of 32 triangles each lane computes the record of
+//     one triangle and the direction (phase constants theta_mid, a/2, b/2,
+//     closed-branch scale factors, series threshold and coefficients) into
+//     LDS; then per batch of 4 triangles lane (t, jj) = (lane / 16,
+//     lane % 16) computes, for triangle t, exp(-i h x_j c) (jj = j < 8, with
+//     the series value of the wave's smallest radius with offset j) or the
+//     panel-centre phases exp(-i m_p c) of the PG panels of group jj - 8, for
+//     the three constants c;
+//   * mixed form: per batch of 8 triangles lane (t, j) = (lane / 8, lane % 8)
+//     computes the FP32 half-node phases of offset j and the panel-centre
+//     phases of panels w0 + j + 8 q, and lane j = 0 the triangle's constants;
 //   * consumer step: every lane forms its node phases by one complex product
 //     per constant and node and accumulates, reading the batch from LDS.
 //
 // Per-lane sums use FP64 tiles of 32 triangles merged into running totals
-// (the mixed form adds its FP32 contributions in FP64 too); K triangle
-// splits on grid.y as in hsd_direct.hip.
+// (the mixed form sums its closed branch in FP32 over a batch and adds that
+// in FP64); K triangle splits on grid.y as in hsd_direct.hip.
+#include <cstdlib>
 #include <type_traits>
 #include <vector>
 
@@ -33,30 +38,43 @@ namespace hsd {
 
 namespace wv {
 
-constexpr int kTB = 8;        // triangles per batch
+constexpr int kTB = 8;        // triangles per batch (mixed form)
 constexpr int kNH = 8;        // node pairs per panel (16 GL nodes)
-constexpr int kTileBatches = 4;   // batches per FP64 tile sum (32 triangles)
+constexpr int kTB64 = 4;      // triangles per batch (FP64 form, 16 producer lanes each)
+constexpr int kSB64 = 32;     // triangles per record block and tile sum (FP64 form)
 constexpr double kGapFloor = 1e-150;
 constexpr double kGapFloor32 = 1e-18;
 
-// Per-(triangle, direction) constants in LDS.  ce/co are the coefficients of
-// the divided-difference power series as a polynomial in the radius r:
+// Per-(triangle, direction) constants.  ce/co are the coefficients of the
+// divided-difference power series as a polynomial in the radius r:
 // Re = sum_m ce[m] r^(2m), Im = r sum_m co[m] r^(2m) (see series_coefs).
 // FP64 form: series through r^7; the first omitted term is below
 // 9 G^8 / 10! of the leading 1/2, 1e-16 at the largest threshold the form
 // accepts (G < 0.05) and 2.5e-22 at the default 0.01.  For thresholds up to
-// kTauNC3 the consumer sums only through r^5 (first omitted term below
+// kTauNC3 only the terms through r^5 are summed (first omitted term below
 // 7 G^6 / 8! of the leading 1/2: 4e-15 at 0.015, 3.5e-16 at 0.01).
 constexpr int kNC64 = 4;
 constexpr double kTauNC3 = 0.015;
 constexpr int kNC32 = (kMixedSeriesN + 1) / 2;  // through r^kMixedSeriesN (mixed form)
-struct Scal64 { double rthr, pad; double ce[kNC64], co[kNC64]; };   // ce, co carry the factor |J|
 struct Scal32 { float rthr, Ka, Kb, c0lo; float ce[kNC32], co[kNC32]; };   // Ka, Kb, ce, co carry |J|
 
+// FP64 form: one record per triangle of a block of kSB64, written by one lane
+// each and read by the phase producers and consumers of the block's batches.
+struct Rec64 {
+    double tmid, ha, hb;          // phase constants theta_mid, a/2, b/2
+    double ska, skb;              // sqrt(K_a), sqrt(K_b)
+    double rthr, J, pad;          // series threshold tau / G, signed Jacobian
+    double ce[kNC64], co[kNC64];  // carry |J|
+};
+struct Ser64 { double y, x; };    // r^2-scaled series value (Re, Im) at one radius
 template <int PG> struct Batch64 {
-    Scal64 sc[kTB];
-    cs64 Bk[kTB][kNH][3];
-    cs64 Cp[kTB][kNH * PG][3];
+    cs64 Bk[kTB64][kNH][3];
+    cs64 Cp[kTB64][kNH * PG][3];
+    Ser64 S1[kTB64][kNH];         // series value of slot (panel w0, minus) per node offset
+};
+template <int PG> struct Lds64 {
+    Rec64 rec[kSB64];
+    Batch64<PG> b;
 };
 template <int PG> struct Batch32 {
     Scal32 sc[kTB];
@@ -124,21 +142,21 @@ HSD_HD void series_eval(const T ce[kNC64], const T co[kNC64], T r2, T &pe, T &po
     }
 }
 
-// Phase e^{-i h c} of the first panel's centre, held by the first lane of
-// each group of 8 producer lanes (one triangle) when the wave starts at
-// panel 0: broadcast within the group by an LDS swizzle (bit-mask mode, and
-// mask 0x18: every lane reads lane (lane & ~7) of its half-wave).  The host
-// emulation recomputes what that lane computed.
+// Phase e^{-i h c} of the first panel's centre, held by lane 8 of each group
+// of 16 producer lanes (one triangle) when the wave starts at panel 0:
+// broadcast within the group by an LDS swizzle (bit-mask mode, and mask 0x10,
+// or mask 0x08: every lane reads lane (lane & 16) | 8 of its half-wave).  The
+// host emulation recomputes what that lane computed.
 HSD_HD cs64 group_first_phase(cs64 own, double hc, const cs64 *turn)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
     (void)hc;
     (void)turn;
     cs64 r;
-    r.c = __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(own.c), 0x18),
-                           __builtin_amdgcn_ds_swizzle(__double2loint(own.c), 0x18));
-    r.s = __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(own.s), 0x18),
-                           __builtin_amdgcn_ds_swizzle(__double2loint(own.s), 0x18));
+    r.c = __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(own.c), 0x110),
+                           __builtin_amdgcn_ds_swizzle(__double2loint(own.c), 0x110));
+    r.s = __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(own.s), 0x110),
+                           __builtin_amdgcn_ds_swizzle(__double2loint(own.s), 0x110));
     return r;
 #else
     (void)own;
@@ -146,56 +164,103 @@ HSD_HD cs64 group_first_phase(cs64 own, double hc, const cs64 *turn)
 #endif
 }
 
-// Producer, FP64: part j of a triangle's batch entry (the half-node phases
-// of node j and the centre phases of panels w0 + j PG .. w0 + j PG + PG-1).
-// ONE: the wave covers all panels of its direction (w0 = 0); the second
-// panel's phase is then the first one's times e^{-2 i h c}, the square of the
-// group's panel-0 phase, instead of another sin/cos.
-//
-// The closed branch needs K_a sin^2(r a/2), K_a sin(r a/2) cos(r a/2) and
-// the same for b, with K_a = 2 |J| / (G a), K_b = 2 |J| / (G b).  The
-// centre phases of the two half gaps are stored times sqrt(K_a), sqrt(K_b),
-// so the consumer's phase products give sqrt(K) e^{-i r g/2} and the four
-// terms are two squares and two products of their parts.  The sign of J
-// (-1 for a second mesh) rides on the theta_mid half-node phase, the series
-// coefficients carry |J|.
-template <int PG, bool ONE>
-HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
-                      const cs64 *turn, Scal64 *sc, cs64 Bk[3], cs64 Cp[PG][3])
+// Record of a triangle and direction (FP64 form), computed once per pair by
+// one lane.  The closed branch needs K_a sin^2(r a/2), K_a sin(r a/2)
+// cos(r a/2) and the same for b, with K_a = 2 |J| / (G a), K_b = 2 |J| /
+// (G b); their square roots go onto the half-gap phases (see produce64).
+HSD_HD Rec64 make_rec64(const TriDir &td, double tau)
 {
-    const double fr[3] = {td.tmid, 0.5 * td.ac, 0.5 * td.bc};
-    const double hx = hx_tab[j];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        Bk[c] = sincos64_tab(hx * fr[c], turn);
-        Cp[0][c] = sincos64_tab((double)(2 * (w0 + j * PG) + 1) * h * fr[c], turn);
-        if constexpr (ONE && PG > 1) {
-            const cs64 e1 = group_first_phase(Cp[0][c], h * fr[c], turn);
-            const cs64 step = pmul(e1, e1);
-#pragma unroll
-            for (int q = 1; q < PG; ++q) Cp[q][c] = pmul(Cp[q - 1][c], step);
-        } else {
-#pragma unroll
-            for (int q = 1; q < PG; ++q)
-                Cp[q][c] = sincos64_tab((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c], turn);
-        }
-    }
+    Rec64 R;
+    R.tmid = td.tmid;
+    R.ha = 0.5 * td.ac;
+    R.hb = 0.5 * td.bc;
     // 1/ac and 1/bc from one reciprocal of ac bc (both gaps are floored at
     // 1e-150, so the product stays a normal number)
     const double aJ = fabs(td.J);
     const double rab = rcp64(td.ac * td.bc);
     const double t = 2.0 * aJ * td.iG;
-    const double ska = sqrt_pos64(t * (td.bc * rab)), skb = sqrt_pos64(t * (td.ac * rab));
-    if (td.J < 0.0) Bk[0] = cs64{-Bk[0].c, -Bk[0].s};
+    R.ska = sqrt_pos64(t * (td.bc * rab));
+    R.skb = sqrt_pos64(t * (td.ac * rab));
+    R.rthr = tau * td.iG;
+    R.J = td.J;
+    R.pad = 0.0;
+    series_coefs<kNC64>(td.ac, td.bc, aJ, R.ce, R.co);
+    return R;
+}
+
+// Record of a block that a lane computes: lane % kSB64, always in
+// [0, kSB64); the lanes below kSB64 write theirs, the others compute a copy.
+HSD_HD int rec_of_lane(int lane) { return lane % kSB64; }
+
+// Series value (Re, Im, both times r^2) at radius r from a record.
+HSD_HD Ser64 series_at(const Rec64 &R, double r, bool nc3)
+{
+    const double r2 = r * r;
+    double pe, po;
+    if (nc3)
+        series_eval<3>(R.ce, R.co, r2, pe, po);
+    else
+        series_eval<kNC64>(R.ce, R.co, r2, pe, po);
+    return Ser64{r2 * pe, r2 * r * po};
+}
+
+// Phase producer, FP64: lane (t, jj) = (lane / 16, lane % 16) of a batch of
+// kTB64 triangles, one phase per constant c = theta_mid, a/2, b/2.
+//   jj < 8: the half-node phases exp(-i h x_j c) of node offset j = jj, with
+//     the sign of J on the theta_mid one and sqrt(K_a), sqrt(K_b) on the two
+//     half-gap ones (the consumer's phase products then give sqrt(K)
+//     e^{-i r g/2}, and the closed branch's four terms are two squares and
+//     two products of their parts); and the series value of the wave's
+//     smallest-radius slot with that offset (panel w0, radius (2 w0 + 1) h -
+//     h x_j), taken by the consumers where that radius is below the
+//     threshold;
+//   jj >= 8: the panel-centre phases exp(-i m_p c) of panels w0 + j PG + q,
+//     j = jj - 8.  ONE (the wave covers all panels of its direction, w0 = 0):
+//     the second panel's phase is the first one's times e^{-2 i h c}, the
+//     square of the phase of the first panel's centre, which lane jj = 8
+//     holds.
+template <int PG, bool ONE>
+HSD_HD void produce64(const Rec64 &rec, double h, const double *hx_tab, int jj, int w0, bool nc3,
+                      const cs64 *turn, cs64 Bk[3], cs64 (*Cp)[3], Ser64 *s1)
+{
+    // The whole record is read up front and every lane runs the same
+    // arithmetic (a half-node lane's factors on the phases, 1 for a
+    // panel-centre lane), so the role only picks where the results go.
+    const Rec64 R = rec;
+    const bool half = jj < kNH;
+    const int j = jj & (kNH - 1);
+    const double hxj = hx_tab[j];
+    const double mult = half ? hxj : (double)(2 * (w0 + j * PG) + 1) * h;
+    const double fr[3] = {R.tmid, R.ha, R.hb};
+    const double fac[3] = {half && R.J < 0.0 ? -1.0 : 1.0, half ? R.ska : 1.0, half ? R.skb : 1.0};
+    cs64 ph[3], step[3];
 #pragma unroll
-    for (int q = 0; q < PG; ++q) {
-        Cp[q][1] = cs64{ska * Cp[q][1].c, ska * Cp[q][1].s};
-        Cp[q][2] = cs64{skb * Cp[q][2].c, skb * Cp[q][2].s};
+    for (int c = 0; c < 3; ++c) ph[c] = sincos64_tab(mult * fr[c], turn);
+    if constexpr (ONE && PG > 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const cs64 e1 = group_first_phase(ph[c], h * fr[c], turn);
+            step[c] = pmul(e1, e1);
+        }
     }
-    if (sc) {
-        sc->rthr = tau * td.iG;
-        sc->pad = 0.0;
-        series_coefs<kNC64>(td.ac, td.bc, aJ, sc->ce, sc->co);
+    const Ser64 sv = series_at(R, (double)(2 * w0 + 1) * h - hxj, nc3);
+    cs64 *dst = half ? Bk : Cp[0];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) dst[c] = cs64{fac[c] * ph[c].c, fac[c] * ph[c].s};
+    if (half) {
+        *s1 = sv;
+    } else {
+#pragma unroll
+        for (int q = 1; q < PG; ++q) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if constexpr (ONE)
+                    ph[c] = pmul(ph[c], step[c]);
+                else
+                    ph[c] = sincos64_tab((double)(2 * (w0 + j * PG + q) + 1) * h * fr[c], turn);
+                Cp[q][c] = ph[c];
+            }
+        }
     }
 }
 
@@ -210,14 +275,18 @@ HSD_HD void produce64(const TriDir &td, double h, const double *hx_tab, int j, i
 // The series branch replaces the closed one where r < tau / G.  Within a
 // lane the slot (pl 0, minus) has the smallest radius; r_others is the
 // smallest radius of any other slot over the whole wave ((2 w0 + 1) h +
-// h x_0), so when the triangle's threshold is not above it only that slot
-// can take the series, and the others skip their compare.  nc3: thresholds
-// up to kTauNC3, series through r^5.
+// h x_0).  While the triangle's threshold is not above r_others, only that
+// slot of the lanes of the first panel group (radius (2 w0 + 1) h - h x_k)
+// can be below it, and those lanes take the series value the producer
+// stored (s1); otherwise every slot compares and evaluates the series from
+// the record.  nc3: thresholds up to kTauNC3, series through r^5.
 template <int PG>
-HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 (*Cp)[3], double h,
+HSD_HD void consume64(const Rec64 &R, const cs64 Bk[3], const cs64 (*Cp)[3], const Ser64 &s1, double h,
                       double hx, int pbase, double r_others, bool nc3, double *acc_re, double *acc_im)
 {
     constexpr int NS = 2 * PG;
+    const double rthr = R.rthr;
+    const Ser64 sv = s1;
     double Yr[NS], Xr[NS], rs[NS];
 #pragma unroll
     for (int pl = 0; pl < PG; ++pl) {
@@ -233,21 +302,21 @@ HSD_HD void consume64(const Scal64 &sc, const cs64 Bk[3], const cs64 (*Cp)[3], d
             Xr[slot] = __builtin_fma(E2.s, E2.c, -(E1.s * E1.c));
         }
     }
-    auto series = [&](int slot) {
-        const double r = rs[slot], r2 = r * r;
-        double pe, po;
-        if (nc3)
-            series_eval<3>(sc.ce, sc.co, r2, pe, po);
-        else
-            series_eval<kNC64>(sc.ce, sc.co, r2, pe, po);
-        Yr[slot] = r2 * pe;
-        Xr[slot] = r2 * r * po;
-    };
-    if (rs[1] < sc.rthr) series(1);
-    if (sc.rthr > r_others) {
+    // the stored series value is taken without a branch; where it does not
+    // belong to this slot (a later panel group) the triangle takes the
+    // compare-every-slot path below, which overwrites it
+    const bool take = rs[1] < rthr;
+    Yr[1] = take ? sv.y : Yr[1];
+    Xr[1] = take ? sv.x : Xr[1];
+    if (rthr > r_others) {
 #pragma unroll
-        for (int slot = 0; slot < NS; ++slot)
-            if (slot != 1 && rs[slot] < sc.rthr) series(slot);
+        for (int slot = 0; slot < NS; ++slot) {
+            if (rs[slot] < rthr) {
+                const Ser64 v = series_at(R, rs[slot], nc3);
+                Yr[slot] = v.y;
+                Xr[slot] = v.x;
+            }
+        }
     }
 #pragma unroll
     for (int pl = 0; pl < PG; ++pl) {
@@ -408,24 +477,38 @@ HSD_HD const TriRec *tri_at(const TriRec *A, int64_t nA, const TriRec *B, int64_
 } // namespace wv
 
 // ---------------------------------------------------------------------------
-// kernel body: 4 waves per block, one direction (and panel window) per wave
+// kernel bodies: 4 waves per block, one direction (and panel window) per wave
 // ---------------------------------------------------------------------------
-template <int PG, int FORM, bool ONE>
-__device__ __forceinline__ void direct_wave_body(
+
+// Slot -> output node: panel p, sign sg (0: m_p + h x_k), r^2 divided out.
+__device__ __forceinline__ void store_slot(double2 *out, int p, int sg, int k, double h, double hx, double re,
+                                           double im)
+{
+    const double m = (double)(2 * p + 1) * h;
+    const double r = sg == 0 ? m + hx : m - hx;
+    const double inv = 1.0 / (r * r);
+    const int jn = sg == 0 ? wv::kNH + k : wv::kNH - 1 - k;
+    out[(int64_t)p * (2 * wv::kNH) + jn] = make_double2(re * inv, im * inv);
+}
+
+// FP64 form.  Per block of kSB64 triangles: lane l < kSB64 writes the record
+// of triangle l; then per batch of kTB64 triangles the 64 lanes produce the
+// phases (produce64) and every lane consumes the batch (consume64).  The
+// lane's slots are summed in FP64 over the block (a tile of kSB64
+// triangles) and merged into the running totals after it.
+template <int PG, bool ONE>
+__device__ __forceinline__ void direct_wave_body64(
     const TriRec *__restrict__ A, int64_t nA, const TriRec *__restrict__ B, int64_t nB,
     const double *__restrict__ dirs, const double *__restrict__ hx_tab, int64_t d_begin, int64_t d_count,
     int P, double h, double tau, int64_t N, double2 *__restrict__ partial)
 {
     using namespace wv;
     constexpr int NS = 2 * PG;
-    constexpr bool F64 = FORM == HSD_FORM_FP64;
-    __shared__ typename std::conditional<F64, Batch64<PG>, Batch32<PG>>::type lds[4];
-    __shared__ cs64 turn[F64 ? 32 : 1];     // e^{i k pi/16} for the FP64 sin/cos
+    __shared__ Lds64<PG> lds[4];
+    __shared__ cs64 turn[32];     // e^{i k pi/16} for the FP64 sin/cos
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if constexpr (F64) {
-        if (threadIdx.x < 32) turn[threadIdx.x] = turn16((int)threadIdx.x);
-        __syncthreads();
-    }
+    if (threadIdx.x < 32) turn[threadIdx.x] = turn16((int)threadIdx.x);
+    __syncthreads();
     const int wpd = P / (kNH * PG);                 // waves per direction
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
     const bool valid = gw < d_count * wpd;
@@ -434,17 +517,11 @@ __device__ __forceinline__ void direct_wave_body(
     const int w0 = (int)(GW % wpd) * kNH * PG;       // first panel of the wave
     const double nx = dirs[3 * d], ny = dirs[3 * d + 1], nz = dirs[3 * d + 2];
     const int k = lane & 7, g = lane >> 3;             // consumer roles
-    const int pt = lane >> 3, pj = lane & 7;           // producer roles
+    const int pt = lane >> 4, pj = lane & 15;          // phase producer roles
     const double hx = hx_tab[k];
-    // FP64 consumer slots (pl, sg) hold panel pbase + pl; mixed-form lanes
-    // are laid out as (po, sg, k), see consume32
-    const int pbase = w0 + g * PG;
-    const int po = lane >> 4, sgl = (lane >> 3) & 1;
-    float rf[F64 ? 1 : NS], r2f[F64 ? 1 : NS];
-    double r2d[F64 ? 1 : NS];
+    const int pbase = w0 + g * PG;                     // slots (pl, sg): panel pbase + pl
     const double r_others = (double)(2 * w0 + 1) * h + hx_tab[0];   // see consume64
     const bool nc3 = tau <= kTauNC3;
-    if constexpr (!F64) mixed_lane_radii<PG>(w0, po, sgl, h, hx, rf, r2f, r2d);
     auto &L = lds[w];
 
     const int64_t ntot = nA + nB;
@@ -452,90 +529,127 @@ __device__ __forceinline__ void direct_wave_body(
     const int64_t t_begin = ntot * blockIdx.y / K;
     const int64_t t_end = ntot * (blockIdx.y + 1) / K;
 
-    // FP64 form: FP64 tile sums over kTileBatches batches merged into the
-    // running totals; mixed form: the closed branch's FP32 sums over one
-    // batch flushed into the FP64 running totals after every batch (the
-    // series branch adds to the running totals directly, see consume32)
-    using Acc = typename std::conditional<F64, double, float>::type;
-    double tot_re[NS], tot_im[NS];
-    Acc acc_re[NS], acc_im[NS];
+    double tot_re[NS], tot_im[NS], acc_re[NS], acc_im[NS];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) { tot_re[i] = 0.0; tot_im[i] = 0.0; acc_re[i] = 0; acc_im[i] = 0; }
+    for (int i = 0; i < NS; ++i) { tot_re[i] = 0.0; tot_im[i] = 0.0; acc_re[i] = 0.0; acc_im[i] = 0.0; }
 
-    int nb = 0;
+    for (int64_t sb = t_begin; sb < t_end; sb += kSB64) {
+        const int nsb = (int)((t_end - sb) < kSB64 ? (t_end - sb) : kSB64);
+        {   // records (lanes l and l + 32 compute the same one)
+            const int l = rec_of_lane(lane);
+            double J;
+            const TriRec *rp = wv::tri_at(A, nA, B, sb + (l < nsb ? l : 0), J);
+            const Rec64 R = make_rec64(tri_dir(*rp, J, nx, ny, nz, kGapFloor), tau);
+            if (lane < kSB64) L.rec[l] = R;
+        }
+        wave_lds_sync();
+        for (int b0 = 0; b0 < nsb; b0 += kTB64) {
+            const int nvalid = (nsb - b0) < kTB64 ? (nsb - b0) : kTB64;
+            const int j = pj & (kNH - 1);
+            produce64<PG, ONE>(L.rec[b0 + (pt < nvalid ? pt : 0)], h, hx_tab, pj, w0, nc3, turn, L.b.Bk[pt][j],
+                               &L.b.Cp[pt][j * PG], &L.b.S1[pt][j]);
+            wave_lds_sync();
+#pragma unroll
+            for (int t = 0; t < kTB64; ++t)   // unrolled: the batch offsets become immediates
+                if (t < nvalid)
+                    consume64<PG>(L.rec[b0 + t], L.b.Bk[t][k], &L.b.Cp[t][g * PG], L.b.S1[t][k], h, hx, pbase,
+                                  r_others, nc3, acc_re, acc_im);
+            wave_lds_sync();
+        }
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            tot_re[i] += acc_re[i];
+            tot_im[i] += acc_im[i];
+            acc_re[i] = 0.0;
+            acc_im[i] = 0.0;
+        }
+    }
+    if (!valid) return;
+    double2 *out = partial + (int64_t)blockIdx.y * N + d * (int64_t)(P * 2 * kNH);
+#pragma unroll
+    for (int slot = 0; slot < NS; ++slot)
+        store_slot(out, pbase + slot / 2, slot % 2, k, h, hx, tot_re[slot], tot_im[slot]);
+}
+
+// Mixed form: batches of kTB triangles, lane (t, j) = (lane / 8, lane % 8)
+// producing part j of triangle t (produce32); the closed branch's FP32 sums
+// over one batch are flushed into the FP64 running totals after every batch
+// (the series branch adds to the running totals directly, see consume32).
+template <int PG>
+__device__ __forceinline__ void direct_wave_body32(
+    const TriRec *__restrict__ A, int64_t nA, const TriRec *__restrict__ B, int64_t nB,
+    const double *__restrict__ dirs, const double *__restrict__ hx_tab, int64_t d_begin, int64_t d_count,
+    int P, double h, double tau, int64_t N, double2 *__restrict__ partial)
+{
+    using namespace wv;
+    constexpr int NS = 2 * PG;
+    __shared__ Batch32<PG> lds[4];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wpd = P / (kNH * PG);                 // waves per direction
+    const int64_t gw = (int64_t)blockIdx.x * 4 + w;
+    const bool valid = gw < d_count * wpd;
+    const int64_t GW = valid ? gw : 0;
+    const int64_t d = d_begin + GW / wpd;
+    const int w0 = (int)(GW % wpd) * kNH * PG;       // first panel of the wave
+    const double nx = dirs[3 * d], ny = dirs[3 * d + 1], nz = dirs[3 * d + 2];
+    const int k = lane & 7;
+    const int pt = lane >> 3, pj = lane & 7;           // producer roles
+    const double hx = hx_tab[k];
+    // lanes are laid out as (po, sg, k), see consume32
+    const int po = lane >> 4, sgl = (lane >> 3) & 1;
+    float rf[NS], r2f[NS];
+    double r2d[NS];
+    mixed_lane_radii<PG>(w0, po, sgl, h, hx, rf, r2f, r2d);
+    auto &L = lds[w];
+
+    const int64_t ntot = nA + nB;
+    const int K = gridDim.y;
+    const int64_t t_begin = ntot * blockIdx.y / K;
+    const int64_t t_end = ntot * (blockIdx.y + 1) / K;
+
+    double tot_re[NS], tot_im[NS];
+    float acc_re[NS], acc_im[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) { tot_re[i] = 0.0; tot_im[i] = 0.0; acc_re[i] = 0.0f; acc_im[i] = 0.0f; }
+
     for (int64_t tb = t_begin; tb < t_end; tb += kTB) {
         const int nvalid = (int)((t_end - tb) < kTB ? (t_end - tb) : kTB);
         {   // produce
             const int64_t gi = tb + (pt < nvalid ? pt : 0);
             double J;
             const TriRec *rp = wv::tri_at(A, nA, B, gi, J);
-            const TriDir td = tri_dir(*rp, J, nx, ny, nz, F64 ? kGapFloor : kGapFloor32);
-            if constexpr (F64)
-                produce64<PG, ONE>(td, h, hx_tab, pj, w0, tau, turn, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
-                                   &L.Cp[pt][pj * PG]);
-            else
-                produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
-                              L.Cp[pt]);
+            const TriDir td = tri_dir(*rp, J, nx, ny, nz, kGapFloor32);
+            produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj], L.Cp[pt]);
         }
         wave_lds_sync();
-        for (int t = 0; t < nvalid; ++t) {
-            if constexpr (F64)
-                consume64<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][g * PG], h, hx, pbase, r_others, nc3, acc_re, acc_im);
-            else
-                consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1, acc_re, acc_im, tot_re,
-                              tot_im);
-        }
+        for (int t = 0; t < nvalid; ++t)
+            consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1, acc_re, acc_im, tot_re, tot_im);
         wave_lds_sync();
-        if constexpr (F64) {
-            if (++nb == kTileBatches) {
-                nb = 0;
 #pragma unroll
-                for (int i = 0; i < NS; ++i) {
-                    tot_re[i] += acc_re[i];
-                    tot_im[i] += acc_im[i];
-                    acc_re[i] = 0.0;
-                    acc_im[i] = 0.0;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < NS; ++i) {
-                tot_re[i] += (double)acc_re[i];
-                tot_im[i] += (double)acc_im[i];
-                acc_re[i] = 0.0f;
-                acc_im[i] = 0.0f;
-            }
+        for (int i = 0; i < NS; ++i) {
+            tot_re[i] += (double)acc_re[i];
+            tot_im[i] += (double)acc_im[i];
+            acc_re[i] = 0.0f;
+            acc_im[i] = 0.0f;
         }
-    }
-    if constexpr (F64) {
-#pragma unroll
-        for (int i = 0; i < NS; ++i) { tot_re[i] += acc_re[i]; tot_im[i] += acc_im[i]; }
     }
     if (!valid) return;
     double2 *out = partial + (int64_t)blockIdx.y * N + d * (int64_t)(P * 2 * kNH);
 #pragma unroll
-    for (int slot = 0; slot < NS; ++slot) {
-        // slot -> (panel, sign): (pbase + slot / 2, slot % 2) in FP64,
-        // (w0 + po + 4 slot, sgl) in the mixed form
-        const int p = F64 ? pbase + slot / 2 : w0 + po + 4 * slot;
-        const int sg = F64 ? slot % 2 : sgl;
-        const double m = (double)(2 * p + 1) * h;
-        const double r = sg == 0 ? m + hx : m - hx;
-        const double inv = 1.0 / (r * r);
-        const int jn = sg == 0 ? kNH + k : kNH - 1 - k;
-        out[(int64_t)p * (2 * kNH) + jn] = make_double2(tot_re[slot] * inv, tot_im[slot] * inv);
-    }
+    for (int slot = 0; slot < NS; ++slot)   // slot -> panel w0 + po + 4 slot, sign sgl
+        store_slot(out, w0 + po + 4 * slot, sgl, k, h, hx, tot_re[slot], tot_im[slot]);
 }
 
-// FP64 form: its LDS batch (9.75 KB per wave, 39.5 KB per block) allows 4
-// blocks per CU.  ONE: one wave per direction (the wave starts at panel 0).
+// FP64 form: its LDS (9 KB per wave: 32 records and one batch, 36.5 KB per
+// block) allows 4 blocks per CU.  ONE: one wave per direction (the wave
+// starts at panel 0).
 template <int PG, bool ONE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_direct_wave(
     const TriRec *__restrict__ A, int64_t nA, const TriRec *__restrict__ B, int64_t nB,
     const double *__restrict__ dirs, const double *__restrict__ hx_tab, int64_t d_begin, int64_t d_count,
     int P, double h, double tau, int64_t N, double2 *__restrict__ partial)
 {
-    direct_wave_body<PG, HSD_FORM_FP64, ONE>(A, nA, B, nB, dirs, hx_tab, d_begin, d_count, P, h, tau, N, partial);
+    direct_wave_body64<PG, ONE>(A, nA, B, nB, dirs, hx_tab, d_begin, d_count, P, h, tau, N, partial);
 }
 
 // Mixed form: its 7 KB of LDS per wave leave the registers as the limit;
@@ -547,7 +661,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     const double *__restrict__ dirs, const double *__restrict__ hx_tab, int64_t d_begin, int64_t d_count,
     int P, double h, double tau, int64_t N, double2 *__restrict__ partial)
 {
-    direct_wave_body<PG, HSD_FORM_MIXED, false>(A, nA, B, nB, dirs, hx_tab, d_begin, d_count, P, h, tau, N, partial);
+    direct_wave_body32<PG>(A, nA, B, nB, dirs, hx_tab, d_begin, d_count, P, h, tau, N, partial);
 }
 
 bool wave_kernel_applies(const hsd_rule *rule)
@@ -605,90 +719,121 @@ hsd_status launch_direct_wave(hipStream_t st, const MeshPair &mp, const hsd_rule
 // ---------------------------------------------------------------------------
 // host emulation of one direction (self checks)
 // ---------------------------------------------------------------------------
-template <int PG, bool F64>
-static void host_wave_dir(const TriRec *A, int64_t nA, double nx, double ny, double nz, const double *hx_tab,
-                          int P, double h, double tau, double *out /* [P*16*2] */)
+// Slot of a lane -> output node (as store_slot).
+static void host_store(double *out, int p, int sg, int k, double h, const double *hx_tab, double re, double im)
+{
+    const double m = (double)(2 * p + 1) * h;
+    const double r = sg == 0 ? m + hx_tab[k] : m - hx_tab[k];
+    const int jn = sg == 0 ? wv::kNH + k : wv::kNH - 1 - k;
+    const int64_t q = (int64_t)p * 16 + jn;
+    out[2 * q] = re / (r * r);
+    out[2 * q + 1] = im / (r * r);
+}
+
+template <int PG>
+static void host_wave_dir64(const TriRec *A, int64_t nA, double nx, double ny, double nz, const double *hx_tab,
+                            int P, double h, double tau, double *out /* [P*16*2] */)
 {
     using namespace wv;
     constexpr int NS = 2 * PG;
     const int wpd = P / (kNH * PG);
-    std::vector<Batch64<PG>> b64(1);
-    std::vector<Batch32<PG>> b32(1);
+    const bool nc3 = tau <= kTauNC3;
+    std::vector<Lds64<PG>> lv(1);
+    auto &L = lv[0];
     cs64 turn[32];
     for (int k = 0; k < 32; ++k) turn[k] = turn16(k);
     for (int wi = 0; wi < wpd; ++wi) {
         const int w0 = wi * kNH * PG;
+        const double r_others = (double)(2 * w0 + 1) * h + hx_tab[0];
+        std::vector<double> tre(64 * NS, 0.0), tim(64 * NS, 0.0), are(64 * NS, 0.0), aim(64 * NS, 0.0);
+        for (int64_t sb = 0; sb < nA; sb += kSB64) {
+            const int nsb = (int)std::min<int64_t>(kSB64, nA - sb);
+            for (int lane = 0; lane < 64; ++lane) {   // as the device lanes, with a bounds check
+                const int l = rec_of_lane(lane);
+                const int64_t gi = sb + (l < nsb ? l : 0);
+                if (l < 0 || l >= kSB64 || gi < 0 || gi >= nA) std::abort();
+                double J;
+                const TriRec *rp = wv::tri_at(A, nA, nullptr, gi, J);
+                const Rec64 R = make_rec64(tri_dir(*rp, J, nx, ny, nz, kGapFloor), tau);
+                if (lane < kSB64) L.rec[l] = R;
+            }
+            for (int b0 = 0; b0 < nsb; b0 += kTB64) {
+                const int nvalid = std::min(kTB64, nsb - b0);
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int pt = lane >> 4, pj = lane & 15, j = pj & (kNH - 1);
+                    const Rec64 &R = L.rec[b0 + (pt < nvalid ? pt : 0)];
+                    if (wpd == 1)
+                        produce64<PG, true>(R, h, hx_tab, pj, w0, nc3, turn, L.b.Bk[pt][j], &L.b.Cp[pt][j * PG],
+                                            &L.b.S1[pt][j]);
+                    else
+                        produce64<PG, false>(R, h, hx_tab, pj, w0, nc3, turn, L.b.Bk[pt][j], &L.b.Cp[pt][j * PG],
+                                             &L.b.S1[pt][j]);
+                }
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int k = lane & 7, g = lane >> 3;
+                    for (int t = 0; t < nvalid; ++t)
+                        consume64<PG>(L.rec[b0 + t], L.b.Bk[t][k], &L.b.Cp[t][g * PG], L.b.S1[t][k], h, hx_tab[k],
+                                      w0 + g * PG, r_others, nc3, &are[lane * NS], &aim[lane * NS]);
+                }
+            }
+            for (int i = 0; i < 64 * NS; ++i) {
+                tre[i] += are[i];
+                tim[i] += aim[i];
+                are[i] = aim[i] = 0.0;
+            }
+        }
+        for (int lane = 0; lane < 64; ++lane) {
+            const int k = lane & 7, g = lane >> 3;
+            for (int slot = 0; slot < NS; ++slot)
+                host_store(out, w0 + g * PG + slot / 2, slot % 2, k, h, hx_tab, tre[lane * NS + slot],
+                           tim[lane * NS + slot]);
+        }
+    }
+}
+
+template <int PG>
+static void host_wave_dir32(const TriRec *A, int64_t nA, double nx, double ny, double nz, const double *hx_tab,
+                            int P, double h, double tau, double *out /* [P*16*2] */)
+{
+    using namespace wv;
+    constexpr int NS = 2 * PG;
+    const int wpd = P / (kNH * PG);
+    std::vector<Batch32<PG>> lv(1);
+    auto &L = lv[0];
+    for (int wi = 0; wi < wpd; ++wi) {
+        const int w0 = wi * kNH * PG;
         std::vector<double> tre(64 * NS, 0.0), tim(64 * NS, 0.0);
-        std::vector<double> are(64 * NS, 0.0), aim(64 * NS, 0.0);
         std::vector<float> fre(64 * NS, 0.0f), fim(64 * NS, 0.0f);
-        int nb = 0;
         for (int64_t tb = 0; tb < nA; tb += kTB) {
             const int nvalid = (int)std::min<int64_t>(kTB, nA - tb);
             for (int lane = 0; lane < 64; ++lane) {
                 const int pt = lane >> 3, pj = lane & 7;
                 double J;
                 const TriRec *rp = wv::tri_at(A, nA, nullptr, tb + (pt < nvalid ? pt : 0), J);
-                const TriDir td = tri_dir(*rp, J, nx, ny, nz, F64 ? kGapFloor : kGapFloor32);
-                if (F64) {
-                    auto &L = b64[0];
-                    if (wpd == 1)
-                        produce64<PG, true>(td, h, hx_tab, pj, w0, tau, turn, pj == 0 ? &L.sc[pt] : nullptr,
-                                            L.Bk[pt][pj], &L.Cp[pt][pj * PG]);
-                    else
-                        produce64<PG, false>(td, h, hx_tab, pj, w0, tau, turn, pj == 0 ? &L.sc[pt] : nullptr,
-                                             L.Bk[pt][pj], &L.Cp[pt][pj * PG]);
-                } else {
-                    auto &L = b32[0];
-                    produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj],
-                                  L.Cp[pt]);
-                }
+                const TriDir td = tri_dir(*rp, J, nx, ny, nz, kGapFloor32);
+                produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj], L.Cp[pt]);
             }
             for (int lane = 0; lane < 64; ++lane) {
-                const int k = lane & 7, g = lane >> 3;
-                const int pbase = w0 + g * PG;
+                const int k = lane & 7;
                 const int po = lane >> 4, sgl = (lane >> 3) & 1;
                 float rf[NS], r2f[NS];
                 double r2d[NS];
                 mixed_lane_radii<PG>(w0, po, sgl, h, hx_tab[k], rf, r2f, r2d);
-                for (int t = 0; t < nvalid; ++t) {
-                    if (F64) {
-                        auto &L = b64[0];
-                        consume64<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][g * PG], h, hx_tab[k], pbase,
-                                      (double)(2 * w0 + 1) * h + hx_tab[0], tau <= kTauNC3, &are[lane * NS],
-                                      &aim[lane * NS]);
-                    } else {
-                        auto &L = b32[0];
-                        consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1, &fre[lane * NS],
-                                      &fim[lane * NS], &tre[lane * NS], &tim[lane * NS]);
-                    }
-                }
+                for (int t = 0; t < nvalid; ++t)
+                    consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1, &fre[lane * NS],
+                                  &fim[lane * NS], &tre[lane * NS], &tim[lane * NS]);
             }
-            if (!F64 || ++nb == kTileBatches) {
-                nb = 0;
-                for (int i = 0; i < 64 * NS; ++i) {
-                    tre[i] += F64 ? are[i] : (double)fre[i];
-                    tim[i] += F64 ? aim[i] : (double)fim[i];
-                    are[i] = aim[i] = 0.0;
-                    fre[i] = fim[i] = 0.0f;
-                }
+            for (int i = 0; i < 64 * NS; ++i) {
+                tre[i] += (double)fre[i];
+                tim[i] += (double)fim[i];
+                fre[i] = fim[i] = 0.0f;
             }
         }
         for (int lane = 0; lane < 64; ++lane) {
-            const int k = lane & 7, g = lane >> 3;
+            const int k = lane & 7;
             const int po = lane >> 4, sgl = (lane >> 3) & 1;
-            for (int slot = 0; slot < NS; ++slot) {
-                const int i = lane * NS + slot;
-                const double re = tre[i] + are[i];
-                const double im = tim[i] + aim[i];
-                const int p = F64 ? w0 + g * PG + slot / 2 : w0 + po + 4 * slot;
-                const int sg = F64 ? slot % 2 : sgl;
-                const double m = (double)(2 * p + 1) * h;
-                const double r = sg == 0 ? m + hx_tab[k] : m - hx_tab[k];
-                const int jn = sg == 0 ? kNH + k : kNH - 1 - k;
-                const int64_t q = (int64_t)p * 16 + jn;
-                out[2 * q] = re / (r * r);
-                out[2 * q + 1] = im / (r * r);
-            }
+            for (int slot = 0; slot < NS; ++slot)
+                host_store(out, w0 + po + 4 * slot, sgl, k, h, hx_tab, tre[lane * NS + slot], tim[lane * NS + slot]);
         }
     }
 }
@@ -716,11 +861,11 @@ int hsd__host_transform_wave(const double *verts, const int32_t *tris, int64_t n
         double *o = out + 2 * d * (int64_t)P * 16;
         const double nx = dirs[3 * d], ny = dirs[3 * d + 1], nz = dirs[3 * d + 2];
         if (form == HSD_FORM_FP64) {
-            if (pg2) host_wave_dir<2, true>(rec.data(), nt, nx, ny, nz, hx_tab, P, h, tau, o);
-            else host_wave_dir<1, true>(rec.data(), nt, nx, ny, nz, hx_tab, P, h, tau, o);
+            if (pg2) host_wave_dir64<2>(rec.data(), nt, nx, ny, nz, hx_tab, P, h, tau, o);
+            else host_wave_dir64<1>(rec.data(), nt, nx, ny, nz, hx_tab, P, h, tau, o);
         } else {
-            if (pg2) host_wave_dir<2, false>(rec.data(), nt, nx, ny, nz, hx_tab, P, h, tau, o);
-            else host_wave_dir<1, false>(rec.data(), nt, nx, ny, nz, hx_tab, P, h, tau, o);
+            if (pg2) host_wave_dir32<2>(rec.data(), nt, nx, ny, nz, hx_tab, P, h, tau, o);
+            else host_wave_dir32<1>(rec.data(), nt, nx, ny, nz, hx_tab, P, h, tau, o);
         }
     }
     return 0;

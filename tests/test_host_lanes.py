@@ -222,13 +222,14 @@ def host_wave(v, f, spec, form=0, tau=1e-2):
 @pytest.mark.parametrize("perturb", [True, False])
 def test_wave_kernel_bodies_match_oracle(orc, spec, form, perturb):
     """Producer/consumer bodies of the wave-per-direction kernel, run on the
-    CPU lane by lane, against the oracle at every rule node (ragged last
-    triangle batch: 80 triangles = 10 batches of 8; 20 triangles: ragged)."""
+    CPU lane by lane, against the oracle at every rule node.  75 triangles:
+    two full FP64 record blocks of 32 and a ragged one of 11 (batches of
+    4, 4, 3); for the mixed form 9 batches of 8 and a ragged one of 3."""
     rng = np.random.default_rng(9)
     v, f = icosphere(1)
     if perturb:
         v = rotate(perturb_radial(v, 0.01, rng), random_rotation(rng))
-    f = f[:76]       # ragged batch
+    f = f[:75]       # ragged block and batch
     got = host_wave(v, f, spec, form)
     o = orc.spherical_product_rule(**spec)
     ref = orc.transform(v, f, o.nodes)
@@ -239,6 +240,28 @@ def test_wave_kernel_bodies_match_oracle(orc, spec, form, perturb):
     else:
         assert np.all(np.isfinite(got))
         assert err.max() <= 2e-5 * _area(v, f)
+
+
+@pytest.mark.parametrize("tau", [0.005, 0.015, 0.05])
+@pytest.mark.parametrize("n_panels", [8, 16])
+def test_wave_fp64_series_slot_and_general_path(orc, tau, n_panels):
+    """FP64 wave bodies where the series branch is taken: level-3 triangles
+    (G about 0.1-0.2) against a rule whose first panel reaches down to
+    r = 0.0106 h, so that the smallest-radius slot of the first panel
+    group takes the series value its producer lane stored, and directions
+    near a face normal (small G) send whole triangles through the path that
+    compares every slot.  Elementwise against the oracle; thresholds on
+    both sides of the r^5 / r^7 switch."""
+    rng = np.random.default_rng(21)
+    v, f = icosphere(3)
+    v = rotate(v, random_rotation(rng))
+    f = f[rng.choice(len(f), 70, replace=False)]
+    spec = dict(r_max=2.0 * n_panels, n_panels=n_panels, n_per_panel=16, n_cos=4, n_phi=5)
+    got = host_wave(v, f, spec, 0, tau=tau)
+    o = orc.spherical_product_rule(**spec)
+    ref = orc.transform(v, f, o.nodes, tau=tau)
+    err = np.abs(got - ref)
+    assert np.all(err <= mu_tol(v, f, o.nodes, tau=tau, h=1.0)), err.max()
 
 
 @pytest.mark.parametrize("level", [0, 1, 2])
