@@ -56,7 +56,7 @@ TRIREC_HEADER = "paper_2304_06340_amd/csrc/hsd_internal.hpp"
 # with the hash of KERNEL_SOURCES when they were taken.  A kernel whose
 # sources hash differently reports traffic null: the counters no longer
 # describe it.
-MEASURED_TRAFFIC = {"level7-large-rule": (6.9753e9, "f80df0ca10a0e493")}
+MEASURED_TRAFFIC = {"level7-large-rule": (6.9755e9, "315638415af74bdd")}
 
 
 def kernel_revision() -> str:
@@ -97,15 +97,16 @@ def flops_per_pair(spec, form="fp64") -> float:
     Per pair: 32 + (8 * 106 + 8 * panel lane + 76) / (128 PG) + 1 / 16.
 
     Mixed form (FP32 node arithmetic): consumer 34 per node (the K factors
-    applied to the phase sines: 2 more MUL); producer 20 + 3 (1 + PG) FP32
+    applied to the phase sines: 2 more MUL); per (triangle, wave) a record of
+    20 (dot products, gaps, constants) + 60 (K_a, K_b, threshold and series
+    coefficients through r^11) and 8 producer lanes of 3 (1 + PG) FP32
     sin/cos of 36 each (FP64 reduction 5, polynomials with two-float leading
-    coefficients 31); K_a, K_b, threshold and series coefficients through
-    r^11 once per triangle: 60; batch flush: 2 adds per slot and batch.
+    coefficients 31); batch flush: 2 adds per slot and batch of 8.
     """
     P = spec["n_panels"]
     PG = 2 if P % 16 == 0 else 1
     if form == "mixed":
-        return 34.0 + (20.0 + 3 * (1 + PG) * 36.0 + 60.0 / 8) / (16 * PG) + 2.0 / 8
+        return 34.0 + (8 * 3 * (1 + PG) * 36.0 + 80.0) / (128 * PG) + 2.0 / 8
     one_wave = P == 8 * PG
     panel_lane = 3 * (30.0 + 12.0) if (one_wave and PG == 2) else 3 * PG * 30.0
     return 32.0 + (8 * 106.0 + 8 * panel_lane + 76.0) / (128 * PG) + 1.0 / 16

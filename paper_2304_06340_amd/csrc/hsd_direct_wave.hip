@@ -76,10 +76,21 @@ template <int PG> struct Lds64 {
     Rec64 rec[kSB64];
     Batch64<PG> b;
 };
+// Mixed form: record of a triangle and direction, one per triangle of a
+// block of kSB64 as in the FP64 form; the phase constants stay FP64 (the
+// phases are reduced in FP64).
+struct Rec32 {
+    double tmid, ha, hb;          // phase constants theta_mid, a/2, b/2
+    float sgn, pad;               // sign of J
+    Scal32 sc;
+};
 template <int PG> struct Batch32 {
-    Scal32 sc[kTB];
     cs32 Bk[kTB][kNH][3];
     cs32 Cp[kTB][kNH * PG][3];
+};
+template <int PG> struct Lds32 {
+    Rec32 rec[kSB64];
+    Batch32<PG> b;
 };
 
 // Per-(triangle, direction) constants: sorted gaps (floored), theta_mid and
@@ -340,13 +351,38 @@ HSD_HD void consume64(const Rec64 &R, const cs64 Bk[3], const cs64 (*Cp)[3], con
 // direction, so its FP32 rounding would be the same for every triangle of
 // equal area (a symmetric mesh has few distinct areas) and would not
 // average out: it is kept as the two-float pair ce[0] + c0lo.
-template <int PG>
-HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, int w0, double tau,
-                      Scal32 *sc, cs32 Bk[3], cs32 (*Cp)[3])
+HSD_HD Rec32 make_rec32(const TriDir &td, double tau)
 {
-    const double fr[3] = {td.tmid, 0.5 * td.ac, 0.5 * td.bc};
+    Rec32 R;
+    R.tmid = td.tmid;
+    R.ha = 0.5 * td.ac;
+    R.hb = 0.5 * td.bc;
+    R.sgn = td.J < 0.0 ? -1.0f : 1.0f;
+    R.pad = 0.0f;
+    const double aJ = fabs(td.J);
+    const double rab = rcp64(td.ac * td.bc);   // gaps floored at 1e-18
+    const double t = 2.0 * aJ * td.iG;
+    R.sc.Ka = (float)(t * (td.bc * rab));
+    R.sc.Kb = (float)(t * (td.ac * rab));
+    R.sc.rthr = (float)(fmax(tau, kMixedTau) * td.iG);   // decides the branch only
+    double ce[kNC32], co[kNC32];
+    series_coefs<kNC32>(td.ac, td.bc, aJ, ce, co);
+    R.sc.ce[0] = (float)ce[0];
+    R.sc.c0lo = (float)(ce[0] - (double)R.sc.ce[0]);
+#pragma unroll
+    for (int m = 1; m < kNC32; ++m) R.sc.ce[m] = (float)ce[m];
+#pragma unroll
+    for (int m = 0; m < kNC32; ++m) R.sc.co[m] = (float)co[m];
+    return R;
+}
+
+// Part j of a triangle's phases (mixed form), from its record.
+template <int PG>
+HSD_HD void produce32(const Rec32 &rec, double h, const double *hx_tab, int j, int w0, cs32 Bk[3], cs32 (*Cp)[3])
+{
+    const double fr[3] = {rec.tmid, rec.ha, rec.hb};
     const double hx = hx_tab[j];
-    const float sgn = td.J < 0.0 ? -1.0f : 1.0f;
+    const float sgn = rec.sgn;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         Bk[c] = sincos32_acc(hx * fr[c]);
@@ -356,22 +392,6 @@ HSD_HD void produce32(const TriDir &td, double h, const double *hx_tab, int j, i
             if (c == 0) e = cs32{sgn * e.c, sgn * e.s};
             Cp[j + kNH * q][c] = e;
         }
-    }
-    if (sc) {
-        const double aJ = fabs(td.J);
-        const double rab = rcp64(td.ac * td.bc);   // gaps floored at 1e-18
-        const double t = 2.0 * aJ * td.iG;
-        sc->Ka = (float)(t * (td.bc * rab));
-        sc->Kb = (float)(t * (td.ac * rab));
-        sc->rthr = (float)(fmax(tau, kMixedTau) * td.iG);   // decides the branch only
-        double ce[kNC32], co[kNC32];
-        series_coefs<kNC32>(td.ac, td.bc, aJ, ce, co);
-        sc->ce[0] = (float)ce[0];
-        sc->c0lo = (float)(ce[0] - (double)sc->ce[0]);
-#pragma unroll
-        for (int m = 1; m < kNC32; ++m) sc->ce[m] = (float)ce[m];
-#pragma unroll
-        for (int m = 0; m < kNC32; ++m) sc->co[m] = (float)co[m];
     }
 }
 
@@ -571,10 +591,12 @@ __device__ __forceinline__ void direct_wave_body64(
         store_slot(out, pbase + slot / 2, slot % 2, k, h, hx, tot_re[slot], tot_im[slot]);
 }
 
-// Mixed form: batches of kTB triangles, lane (t, j) = (lane / 8, lane % 8)
-// producing part j of triangle t (produce32); the closed branch's FP32 sums
-// over one batch are flushed into the FP64 running totals after every batch
-// (the series branch adds to the running totals directly, see consume32).
+// Mixed form: per block of kSB64 triangles lane l < kSB64 writes the record
+// of triangle l; then per batch of kTB triangles lane (t, j) = (lane / 8,
+// lane % 8) produces part j of triangle t (produce32); the closed branch's
+// FP32 sums over one batch are flushed into the FP64 running totals after
+// every batch (the series branch adds to the running totals directly, see
+// consume32).
 template <int PG>
 __device__ __forceinline__ void direct_wave_body32(
     const TriRec *__restrict__ A, int64_t nA, const TriRec *__restrict__ B, int64_t nB,
@@ -583,7 +605,7 @@ __device__ __forceinline__ void direct_wave_body32(
 {
     using namespace wv;
     constexpr int NS = 2 * PG;
-    __shared__ Batch32<PG> lds[4];
+    __shared__ Lds32<PG> lds[4];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wpd = P / (kNH * PG);                 // waves per direction
     const int64_t gw = (int64_t)blockIdx.x * 4 + w;
@@ -612,25 +634,31 @@ __device__ __forceinline__ void direct_wave_body32(
 #pragma unroll
     for (int i = 0; i < NS; ++i) { tot_re[i] = 0.0; tot_im[i] = 0.0; acc_re[i] = 0.0f; acc_im[i] = 0.0f; }
 
-    for (int64_t tb = t_begin; tb < t_end; tb += kTB) {
-        const int nvalid = (int)((t_end - tb) < kTB ? (t_end - tb) : kTB);
-        {   // produce
-            const int64_t gi = tb + (pt < nvalid ? pt : 0);
+    for (int64_t sb = t_begin; sb < t_end; sb += kSB64) {
+        const int nsb = (int)((t_end - sb) < kSB64 ? (t_end - sb) : kSB64);
+        {   // records (lanes l and l + 32 compute the same one)
+            const int l = rec_of_lane(lane);
             double J;
-            const TriRec *rp = wv::tri_at(A, nA, B, gi, J);
-            const TriDir td = tri_dir(*rp, J, nx, ny, nz, kGapFloor32);
-            produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj], L.Cp[pt]);
+            const TriRec *rp = wv::tri_at(A, nA, B, sb + (l < nsb ? l : 0), J);
+            const Rec32 R = make_rec32(tri_dir(*rp, J, nx, ny, nz, kGapFloor32), tau);
+            if (lane < kSB64) L.rec[l] = R;
         }
         wave_lds_sync();
-        for (int t = 0; t < nvalid; ++t)
-            consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1, acc_re, acc_im, tot_re, tot_im);
-        wave_lds_sync();
+        for (int b0 = 0; b0 < nsb; b0 += kTB) {
+            const int nvalid = (nsb - b0) < kTB ? (nsb - b0) : kTB;
+            produce32<PG>(L.rec[b0 + (pt < nvalid ? pt : 0)], h, hx_tab, pj, w0, L.b.Bk[pt][pj], L.b.Cp[pt]);
+            wave_lds_sync();
+            for (int t = 0; t < nvalid; ++t)
+                consume32<PG>(L.rec[b0 + t].sc, L.b.Bk[t][k], &L.b.Cp[t][po], rf, r2f, r2d, sgl == 1, acc_re, acc_im,
+                              tot_re, tot_im);
+            wave_lds_sync();
 #pragma unroll
-        for (int i = 0; i < NS; ++i) {
-            tot_re[i] += (double)acc_re[i];
-            tot_im[i] += (double)acc_im[i];
-            acc_re[i] = 0.0f;
-            acc_im[i] = 0.0f;
+            for (int i = 0; i < NS; ++i) {
+                tot_re[i] += (double)acc_re[i];
+                tot_im[i] += (double)acc_im[i];
+                acc_re[i] = 0.0f;
+                acc_im[i] = 0.0f;
+            }
         }
     }
     if (!valid) return;
@@ -652,9 +680,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) voi
     direct_wave_body64<PG, ONE>(A, nA, B, nB, dirs, hx_tab, d_begin, d_count, P, h, tau, N, partial);
 }
 
-// Mixed form: its 7 KB of LDS per wave leave the registers as the limit;
-// held to 128 VGPRs (4 waves per SIMD; a few spills in the producer) it runs
-// about 7% faster than at the 141 it would take.
+// Mixed form: 7.5 KB of LDS per wave (32 records and one batch of 8
+// triangles, 30 KB per block); held to 4 waves per SIMD (128 VGPRs at most).
 template <int PG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_direct_wave_mixed(
     const TriRec *__restrict__ A, int64_t nA, const TriRec *__restrict__ B, int64_t nB,
@@ -798,35 +825,44 @@ static void host_wave_dir32(const TriRec *A, int64_t nA, double nx, double ny, d
     using namespace wv;
     constexpr int NS = 2 * PG;
     const int wpd = P / (kNH * PG);
-    std::vector<Batch32<PG>> lv(1);
+    std::vector<Lds32<PG>> lv(1);
     auto &L = lv[0];
     for (int wi = 0; wi < wpd; ++wi) {
         const int w0 = wi * kNH * PG;
         std::vector<double> tre(64 * NS, 0.0), tim(64 * NS, 0.0);
         std::vector<float> fre(64 * NS, 0.0f), fim(64 * NS, 0.0f);
-        for (int64_t tb = 0; tb < nA; tb += kTB) {
-            const int nvalid = (int)std::min<int64_t>(kTB, nA - tb);
-            for (int lane = 0; lane < 64; ++lane) {
-                const int pt = lane >> 3, pj = lane & 7;
+        for (int64_t sb = 0; sb < nA; sb += kSB64) {
+            const int nsb = (int)std::min<int64_t>(kSB64, nA - sb);
+            for (int lane = 0; lane < 64; ++lane) {   // as the device lanes, with a bounds check
+                const int l = rec_of_lane(lane);
+                const int64_t gi = sb + (l < nsb ? l : 0);
+                if (l < 0 || l >= kSB64 || gi < 0 || gi >= nA) std::abort();
                 double J;
-                const TriRec *rp = wv::tri_at(A, nA, nullptr, tb + (pt < nvalid ? pt : 0), J);
-                const TriDir td = tri_dir(*rp, J, nx, ny, nz, kGapFloor32);
-                produce32<PG>(td, h, hx_tab, pj, w0, tau, pj == 0 ? &L.sc[pt] : nullptr, L.Bk[pt][pj], L.Cp[pt]);
+                const TriRec *rp = wv::tri_at(A, nA, nullptr, gi, J);
+                const Rec32 R = make_rec32(tri_dir(*rp, J, nx, ny, nz, kGapFloor32), tau);
+                if (lane < kSB64) L.rec[l] = R;
             }
-            for (int lane = 0; lane < 64; ++lane) {
-                const int k = lane & 7;
-                const int po = lane >> 4, sgl = (lane >> 3) & 1;
-                float rf[NS], r2f[NS];
-                double r2d[NS];
-                mixed_lane_radii<PG>(w0, po, sgl, h, hx_tab[k], rf, r2f, r2d);
-                for (int t = 0; t < nvalid; ++t)
-                    consume32<PG>(L.sc[t], L.Bk[t][k], &L.Cp[t][po], rf, r2f, r2d, sgl == 1, &fre[lane * NS],
-                                  &fim[lane * NS], &tre[lane * NS], &tim[lane * NS]);
-            }
-            for (int i = 0; i < 64 * NS; ++i) {
-                tre[i] += (double)fre[i];
-                tim[i] += (double)fim[i];
-                fre[i] = fim[i] = 0.0f;
+            for (int b0 = 0; b0 < nsb; b0 += kTB) {
+                const int nvalid = std::min(kTB, nsb - b0);
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int pt = lane >> 3, pj = lane & 7;
+                    produce32<PG>(L.rec[b0 + (pt < nvalid ? pt : 0)], h, hx_tab, pj, w0, L.b.Bk[pt][pj], L.b.Cp[pt]);
+                }
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int k = lane & 7;
+                    const int po = lane >> 4, sgl = (lane >> 3) & 1;
+                    float rf[NS], r2f[NS];
+                    double r2d[NS];
+                    mixed_lane_radii<PG>(w0, po, sgl, h, hx_tab[k], rf, r2f, r2d);
+                    for (int t = 0; t < nvalid; ++t)
+                        consume32<PG>(L.rec[b0 + t].sc, L.b.Bk[t][k], &L.b.Cp[t][po], rf, r2f, r2d, sgl == 1,
+                                      &fre[lane * NS], &fim[lane * NS], &tre[lane * NS], &tim[lane * NS]);
+                }
+                for (int i = 0; i < 64 * NS; ++i) {
+                    tre[i] += (double)fre[i];
+                    tim[i] += (double)fim[i];
+                    fre[i] = fim[i] = 0.0f;
+                }
             }
         }
         for (int lane = 0; lane < 64; ++lane) {
