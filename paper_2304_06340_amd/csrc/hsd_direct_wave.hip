@@ -65,6 +65,7 @@ struct Rec64 {
     double ska, skb;              // sqrt(K_a), sqrt(K_b)
     double rthr, J, pad;          // series threshold tau / G, signed Jacobian
     double ce[kNC64], co[kNC64];  // carry |J|
+    double pad2[2];               // 144 B: the 16-byte units of 16 consecutive records fall in distinct LDS banks
 };
 struct Ser64 { double y, x; };    // r^2-scaled series value (Re, Im) at one radius
 template <int PG> struct Batch64 {
@@ -155,19 +156,19 @@ HSD_HD void series_eval(const T ce[kNC64], const T co[kNC64], T r2, T &pe, T &po
 
 // Phase e^{-i h c} of the first panel's centre, held by lane 8 of each group
 // of 16 producer lanes (one triangle) when the wave starts at panel 0:
-// broadcast within the group by an LDS swizzle (bit-mask mode, and mask 0x10,
-// or mask 0x08: every lane reads lane (lane & 16) | 8 of its half-wave).  The
-// host emulation recomputes what that lane computed.
+// broadcast within the group by a DPP row broadcast (row_newbcast:8, every
+// lane reads lane 8 of its row of 16; a VALU move, no LDS access).  The host
+// emulation recomputes what that lane computed.
 HSD_HD cs64 group_first_phase(cs64 own, double hc, const cs64 *turn)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
     (void)hc;
     (void)turn;
     cs64 r;
-    r.c = __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(own.c), 0x110),
-                           __builtin_amdgcn_ds_swizzle(__double2loint(own.c), 0x110));
-    r.s = __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(own.s), 0x110),
-                           __builtin_amdgcn_ds_swizzle(__double2loint(own.s), 0x110));
+    r.c = __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(own.c), 0x158, 0xf, 0xf, false),
+                           __builtin_amdgcn_mov_dpp(__double2loint(own.c), 0x158, 0xf, 0xf, false));
+    r.s = __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(own.s), 0x158, 0xf, 0xf, false),
+                           __builtin_amdgcn_mov_dpp(__double2loint(own.s), 0x158, 0xf, 0xf, false));
     return r;
 #else
     (void)own;
@@ -195,6 +196,7 @@ HSD_HD Rec64 make_rec64(const TriDir &td, double tau)
     R.rthr = tau * td.iG;
     R.J = td.J;
     R.pad = 0.0;
+    R.pad2[0] = R.pad2[1] = 0.0;
     series_coefs<kNC64>(td.ac, td.bc, aJ, R.ce, R.co);
     return R;
 }
@@ -668,7 +670,7 @@ __device__ __forceinline__ void direct_wave_body32(
         store_slot(out, w0 + po + 4 * slot, sgl, k, h, hx, tot_re[slot], tot_im[slot]);
 }
 
-// FP64 form: its LDS (9 KB per wave: 32 records and one batch, 36.5 KB per
+// FP64 form: its LDS (9.5 KB per wave: 32 records and one batch, 38.5 KB per
 // block) allows 4 blocks per CU.  ONE: one wave per direction (the wave
 // starts at panel 0).
 template <int PG, bool ONE>
