@@ -40,14 +40,15 @@ constexpr double dcosc_coef(int k) { return ((k & 1) ? 1.0 : -1.0) * (2.0 * k - 
 
 // d/dx sin(x)/x and d/dx (1-cos x)/x (x >= 0, ix = 1/x), with the series
 // (k <= 7, first omitted terms far below 1e-16 relative to the leading x/3
-// and 1/2) below 0.05.  Above it the closed forms (cos x - sinc x)/x and
+// and 1/2) below 0.005.  Above it the closed forms (cos x - sinc x)/x and
 // (sin x - (1-cos x)/x)/x lose at most about 6 eps / x^2 to cancellation
-// (2.7e-13 relative at x = 0.05); a lower threshold makes the lanes of a
-// wave (different triangles) take the series less often.
+// (2.6e-11 relative at x = 0.005, against the 1e-9 the gradient is held
+// to); the low threshold makes the lanes of a wave (different triangles)
+// take the series rarely: at 0.05 some lane took it in most iterations.
 HSD_HD void dsinc_dcosc(double x, double ix, double sx, double cx, double sinc, double cosc, double &dsinc,
                         double &dcosc)
 {
-    if (x < 0.05) {
+    if (x < 0.005) {
         const double x2 = x * x;
         double ps = dsinc_coef(7), pc = dcosc_coef(7);
 #pragma unroll
@@ -302,7 +303,10 @@ HSD_HD void adjoint_lane(const TriRec &T, const double *dirs, const double *radi
     }
 }
 
-__global__ __launch_bounds__(256) void k_adjoint(const TriRec *__restrict__ tris, int64_t nt,
+// Held to 3 waves per SIMD (168 VGPRs, a few spills outside the node loop):
+// about 4% faster than the 2 its 204 registers would allow; at 4 the node
+// loop spills.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_adjoint(const TriRec *__restrict__ tris, int64_t nt,
                                                  const double *__restrict__ dirs, int64_t n_dir,
                                                  const double *__restrict__ radii, int n_rad,
                                                  const double2 *__restrict__ resid,
